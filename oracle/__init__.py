@@ -1,0 +1,147 @@
+"""CPU oracle for graphlet counts (test infrastructure only).
+
+Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU library never does, and the
+two share no code: the C source here is compiled on its own with gcc.
+
+Routes (see oracle.c for the definitions each one writes out):
+  bruteforce(g)        every 2/3/4-subset classified by Table 1 (n <= ~300)
+  identity_route(g)    non-induced counts inverted, exact at any size
+  per_edge(g, edges)   |Tri_e|, 4-cliques and induced 4-cycles through e,
+                       literally, one edge at a time
+  bruteforce_edge4     4-cliques / 4-cycles through e by subset enumeration
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+NAMES = ["g2_1", "g2_2", "g3_1", "g3_2", "g3_3", "g3_4"] + [f"g4_{i}" for i in range(1, 12)]
+
+
+class _U128(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_uint64), ("hi", ctypes.c_uint64)]
+
+
+def build() -> str:
+    """Compile the oracle with gcc (plain C, -O2)."""
+    cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-o", _LIB + ".tmp", _SRC]
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        lib.oracle_check_csr.argtypes = [I64, P, P]
+        lib.oracle_check_csr.restype = ctypes.c_int
+        for f in (lib.oracle_bruteforce, lib.oracle_identity_route):
+            f.argtypes = [I64, P, P, ctypes.POINTER(_U128)]
+            f.restype = ctypes.c_int
+        lib.oracle_per_edge.argtypes = [I64, P, P, I64, P, P, P, P, P]
+        lib.oracle_per_edge.restype = ctypes.c_int
+        lib.oracle_bruteforce_edge4.argtypes = [I64, P, P, I64, P, P, P, P]
+        lib.oracle_bruteforce_edge4.restype = ctypes.c_int
+        lib.oracle_edges.argtypes = [I64, P, P, P, P]
+        lib.oracle_edges.restype = I64
+        lib.oracle_classify4.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        lib.oracle_classify4.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _csr(g):
+    rp = np.ascontiguousarray(g.row_ptr, dtype=np.int32)
+    col = np.ascontiguousarray(g.col, dtype=np.int32)
+    if col.size == 0:
+        col = np.zeros(1, dtype=np.int32)
+    return int(g.n), rp, col
+
+
+def _counts(fn, g) -> list[int]:
+    n, rp, col = _csr(g)
+    out = (_U128 * 17)()
+    rc = fn(n, rp.ctypes.data, col.ctypes.data, out)
+    if rc != 0:
+        raise ValueError(f"oracle rejected the graph (code {rc})")
+    return [int(o.lo) | (int(o.hi) << 64) for o in out]
+
+
+def check_csr(g) -> int:
+    n, rp, col = _csr(g)
+    return int(_load().oracle_check_csr(n, rp.ctypes.data, col.ctypes.data))
+
+
+def bruteforce(g) -> list[int]:
+    """17 induced-graphlet counts by enumerating every subset (definition)."""
+    return _counts(_load().oracle_bruteforce, g)
+
+
+def identity_route(g) -> list[int]:
+    """17 induced-graphlet counts from non-induced counts (exact, any size)."""
+    return _counts(_load().oracle_identity_route, g)
+
+
+def classify4(edges: int, maxdeg: int, comps: int) -> int:
+    """Table 1 row (0..10 for g4_1..g4_11) from (edges, Delta, |C|); -1 if none."""
+    return int(_load().oracle_classify4(edges, maxdeg, comps))
+
+
+def edges(g) -> tuple[np.ndarray, np.ndarray]:
+    """Undirected edges (u < v) in canonical order: u ascending, then v."""
+    n, rp, col = _csr(g)
+    lib = _load()
+    m = lib.oracle_edges(n, rp.ctypes.data, col.ctypes.data, None, None)
+    eu = np.empty(max(m, 1), dtype=np.int32)
+    ev = np.empty(max(m, 1), dtype=np.int32)
+    lib.oracle_edges(n, rp.ctypes.data, col.ctypes.data, eu.ctypes.data, ev.ctypes.data)
+    return eu[:m], ev[:m]
+
+
+def per_edge(g, eu, ev) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """(|Tri_e|, 4-cliques through e, induced 4-cycles through e) for each listed edge."""
+    n, rp, col = _csr(g)
+    eu = np.ascontiguousarray(eu, dtype=np.int32)
+    ev = np.ascontiguousarray(ev, dtype=np.int32)
+    k = eu.shape[0]
+    T = np.zeros(max(k, 1), dtype=np.int64)
+    K4 = np.zeros(max(k, 1), dtype=np.int64)
+    C4 = np.zeros(max(k, 1), dtype=np.int64)
+    if k:
+        rc = _load().oracle_per_edge(n, rp.ctypes.data, col.ctypes.data, k, eu.ctypes.data,
+                                     ev.ctypes.data, T.ctypes.data, K4.ctypes.data,
+                                     C4.ctypes.data)
+        if rc != 0:
+            raise ValueError(f"oracle_per_edge failed (code {rc})")
+    return T[:k], K4[:k], C4[:k]
+
+
+def bruteforce_edge4(g, eu, ev) -> tuple[np.ndarray, np.ndarray]:
+    """(4-cliques, induced 4-cycles) containing each listed edge, by subset enumeration."""
+    n, rp, col = _csr(g)
+    eu = np.ascontiguousarray(eu, dtype=np.int32)
+    ev = np.ascontiguousarray(ev, dtype=np.int32)
+    k = eu.shape[0]
+    K4 = np.zeros(max(k, 1), dtype=np.int64)
+    C4 = np.zeros(max(k, 1), dtype=np.int64)
+    if k:
+        rc = _load().oracle_bruteforce_edge4(n, rp.ctypes.data, col.ctypes.data, k,
+                                             eu.ctypes.data, ev.ctypes.data, K4.ctypes.data,
+                                             C4.ctypes.data)
+        if rc != 0:
+            raise ValueError(f"oracle_bruteforce_edge4 failed (code {rc})")
+    return K4[:k], C4[:k]
