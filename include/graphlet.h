@@ -1,0 +1,175 @@
+/*
+ * graphlet.h -- C ABI of the MI355X graphlet counting library.
+ *
+ * Exact counts of all induced 2-, 3- and 4-node graphlets (17 classes,
+ * connected and disconnected) of an undirected simple graph, by the per-edge
+ * method of Ahmed et al., "Graphlet Decomposition: Framework, Algorithms, and
+ * Applications" (arXiv 1506.04322):
+ *   Step 1  per edge e = (u, v): the triangle set Tri_e and the 2-star sets
+ *           Star_u, Star_v (Section 3, the triad census algorithm);
+ *   Step 2  per edge: the 4-cliques and 4-cycles containing e (Section 4,
+ *           Corollaries "cliq" and "cyc", procedures CliqueCount and
+ *           CycleCount of the graphlet counting algorithm);
+ *   Step 3  per edge: the unrestricted counts N_{a,b} in constant time
+ *           (Equations "comb_n_ai_ai" and "comb_n_ai_aj");
+ *   Step 4  all 17 counts from the sums, by the Lemmas of Section 4.3 and
+ *           Equations "g_4_9" and "g_4_11".
+ *
+ * All counting is integer and exact.  Totals are unsigned 128-bit (C(n,3)
+ * exceeds 2^63 from n ~ 3.8 million on).
+ *
+ * Output order of a 17-entry count vector (Table 1 numbering):
+ *   [0] g2_1 edge            [1] g2_2 2-node-independent
+ *   [2] g3_1 triangle        [3] g3_2 2-star
+ *   [4] g3_3 3-node-1-edge   [5] g3_4 3-node-independent
+ *   [6] g4_1 4-clique        [7] g4_2 4-chordalcycle   [8] g4_3 4-tailedtriangle
+ *   [9] g4_4 4-cycle         [10] g4_5 3-star          [11] g4_6 4-path
+ *   [12] g4_7 4-node-1-triangle  [13] g4_8 4-node-2-star  [14] g4_9 4-node-2-edge
+ *   [15] g4_10 4-node-1-edge     [16] g4_11 4-node-independent
+ *
+ * Threading: calls are reentrant; each call uses only its own workspace.
+ * Errors: every entry point returns GC_OK (0) or a negative GC_E* code; the
+ * message of the calling thread's last error is graphlet_last_error().  No
+ * C++ exception crosses this interface.  Outputs are unspecified on error.
+ * Ownership: the library keeps no pointer passed in after a call returns.
+ */
+#ifndef GRAPHLET_H
+#define GRAPHLET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Error codes. */
+#define GC_OK 0
+#define GC_EINVAL (-1)       /* bad argument: null pointer, negative size, odd nnz */
+#define GC_ENOTSORTED (-2)   /* a neighbour list is not strictly increasing (covers duplicates) */
+#define GC_ESELFLOOP (-3)    /* (u, u) present */
+#define GC_EASYMMETRIC (-4)  /* v in N(u) but u not in N(v), or an id outside [0, n) */
+#define GC_EOVERFLOW (-5)    /* a count does not fit the output type */
+#define GC_ENOMEM (-6)       /* workspace too small, or device allocation failed */
+#define GC_EHIP (-7)         /* a HIP runtime call failed */
+#define GC_EINTERNAL (-8)    /* an exact division left a remainder: never expected */
+
+/* Flags. */
+#define GC_VALIDATE 1u /* check the CSR contract on the device first, O(m log Delta) */
+
+/*
+ * An undirected simple graph in CSR form, in DEVICE memory owned by the
+ * caller.  The paper's input is G = (V, E) undirected, with weights, loops and
+ * direction discarded (Section 5, setup).
+ *   n        number of vertices, all of them counted in |V| (isolated ones
+ *            too); 0 <= n < 2^31
+ *   nnz      2 |E|: every edge appears in both endpoint lists; nnz < 2^31
+ *   row_ptr  int32[n+1], row_ptr[0] = 0, row_ptr[n] = nnz, non-decreasing
+ *   col      int32[nnz], each list strictly increasing, ids in [0, n),
+ *            no (u, u), symmetric
+ * Inputs that break the contract give unspecified counts unless
+ * GC_VALIDATE is set, in which case they are rejected with the codes above.
+ */
+typedef struct gc_csr {
+  int64_t n;
+  int64_t nnz;
+  const int32_t *row_ptr;
+  const int32_t *col;
+} gc_csr;
+
+/* Unsigned 128-bit integer: value = hi * 2^64 + lo. */
+typedef struct gc_u128 {
+  uint64_t lo;
+  uint64_t hi;
+} gc_u128;
+
+/*
+ * Bytes of device workspace graphlet_count needs for this graph (per_edge:
+ * whether per_edge_out will be requested).  Reads g->n and g->nnz only on the
+ * host, plus the maximum degree on the device (one small stream-ordered read
+ * on `stream`, a hipStream_t).  Returns 0 if the sizes are invalid.
+ */
+size_t graphlet_workspace_size(const gc_csr *g, int per_edge, void *stream);
+
+/*
+ * Global counts, and optionally per-edge quantities, of one graph.
+ *   g             the graph (device arrays, see gc_csr)
+ *   out_counts    HOST gc_u128[17], the 17 counts in the order above
+ *   per_edge_out  NULL, or DEVICE int64[3*m] (m = nnz/2), filled with
+ *                 [0*m + k] |Tri_e|        (triangles through e, Section 3)
+ *                 [1*m + k] 4-cliques containing e  (Corollary "cliq")
+ *                 [2*m + k] induced 4-cycles containing e (Corollary "cyc")
+ *                 where k is the canonical id of e = (u, v), u < v: edges
+ *                 numbered u ascending, then v ascending as in u's list.
+ *   workspace     DEVICE buffer of ws_bytes >= graphlet_workspace_size(),
+ *                 or NULL to let the library allocate (and free) its own
+ *   stream        hipStream_t the work is ordered on (NULL = default stream)
+ *   flags         GC_VALIDATE or 0
+ * Returns after out_counts is filled; per_edge_out is complete when the
+ * call returns.  Device memory the caller passed is only read, except
+ * per_edge_out and workspace.
+ */
+int graphlet_count(const gc_csr *g, gc_u128 out_counts[17], int64_t *per_edge_out,
+                   void *workspace, size_t ws_bytes, void *stream, uint32_t flags);
+
+/*
+ * Many small graphs in one call (the paper's graph-classification use, many
+ * small networks each described by its k = 2, 3, 4 counts, Section 6).
+ *   graphs    G >= 0
+ *   node_off  DEVICE int64[G+1]: graph i owns rows node_off[i] .. node_off[i+1]-1
+ *             of the concatenated row_ptr; every graph has at most
+ *             GC_BATCH_MAX_N vertices
+ *   row_ptr   DEVICE int32[node_off[G]+1], offsets into col (global)
+ *   col       DEVICE int32[...], vertex ids LOCAL to each graph (0..n_i-1),
+ *             per-graph lists obey the gc_csr contract
+ * out: DEVICE int64[G][17], the 17 counts of each graph in the order above
+ * (every count of a graph with at most GC_BATCH_MAX_N vertices fits int64).
+ * Stream-ordered; returns when the results are complete.
+ */
+#define GC_BATCH_MAX_N 1024
+typedef struct gc_batch {
+  int64_t graphs;
+  const int64_t *node_off;
+  const int32_t *row_ptr;
+  const int32_t *col;
+} gc_batch;
+
+int graphlet_count_batched(const gc_batch *b, int64_t *out, void *stream, uint32_t flags);
+
+/*
+ * Diagnostics.  When enabled (per calling thread), graphlet_count records HIP
+ * events on its stream at the boundaries of its phases, and the durations of
+ * the thread's last call can be read back, together with the amount of
+ * adjacency work each counting phase performed (the algorithmic units the
+ * phases are measured against).  Phases:
+ *   0 prepass   relabelling by degree, re-sorted lists, work lists
+ *   1 cliques   Step 1 and Step 2a (triangles, 4-cliques)
+ *   2 cyc-light Step 2b for vertices with few wedges
+ *   3 cyc-heavy Step 2b for vertices with many wedges
+ *   4 per-edge  per-edge 4-cliques and D_e (only with per_edge_out)
+ *   5 step3     Step 3 sums and their reduction
+ * Enabling costs one event record per phase; results are unchanged.
+ */
+#define GC_PHASES 6
+typedef struct gc_timing {
+  double ms[GC_PHASES];      /* device time per phase, milliseconds */
+  uint64_t clique_entries;   /* upper-list entries scanned by phase 1 */
+  uint64_t wedges_light;     /* wedges aggregated by phase 2 */
+  uint64_t wedges_heavy;     /* wedges aggregated by phase 3 */
+  int64_t heavy_items;       /* work items of phase 3 */
+} gc_timing;
+
+void graphlet_timing_enable(int on);
+int graphlet_last_timing(gc_timing *out);
+
+/* Message of the calling thread's most recent error ("" if none). */
+const char *graphlet_last_error(void);
+
+/* Library version string. */
+const char *graphlet_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRAPHLET_H */

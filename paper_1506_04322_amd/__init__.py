@@ -1,0 +1,209 @@
+"""Python binding of the MI355X graphlet counting library (libgraphlet.so).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libgraphlet.so.  PyTorch supplies device memory and the stream.
+There is no fallback: if the library is not built, or no GPU is visible, the
+calls raise.
+
+The entry points mirror include/graphlet.h:
+  graphlet_count(row_ptr, col, n, per_edge=False, workspace=None, validate=False)
+  graphlet_workspace_size(row_ptr, col, n, per_edge=False)
+  graphlet_count_batched(node_off, row_ptr, col)
+  graphlet_last_error()
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgraphlet.so")
+
+NAMES = ["g2_1", "g2_2", "g3_1", "g3_2", "g3_3", "g3_4"] + [f"g4_{i}" for i in range(1, 12)]
+
+GC_VALIDATE = 1
+ERRORS = {
+    -1: "GC_EINVAL", -2: "GC_ENOTSORTED", -3: "GC_ESELFLOOP", -4: "GC_EASYMMETRIC",
+    -5: "GC_EOVERFLOW", -6: "GC_ENOMEM", -7: "GC_EHIP", -8: "GC_EINTERNAL",
+}
+BATCH_MAX_N = 1024
+
+
+class GraphletError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p)]
+
+
+class _Batch(ctypes.Structure):
+    _fields_ = [("graphs", ctypes.c_int64), ("node_off", ctypes.c_void_p),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p)]
+
+
+class _U128(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_uint64), ("hi", ctypes.c_uint64)]
+
+
+_lib = None
+
+# Every symbol include/graphlet.h declares.
+EXPORTS = [
+    "graphlet_workspace_size",
+    "graphlet_count",
+    "graphlet_count_batched",
+    "graphlet_last_error",
+    "graphlet_version",
+    "graphlet_timing_enable",
+    "graphlet_last_timing",
+]
+
+PHASES = ["prepass", "cliques", "cyc_light", "cyc_heavy", "per_edge", "step3"]
+
+
+class _Timing(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 6), ("clique_entries", ctypes.c_uint64),
+                ("wedges_light", ctypes.c_uint64), ("wedges_heavy", ctypes.c_uint64),
+                ("heavy_items", ctypes.c_int64)]
+
+
+def load():
+    """Loads libgraphlet.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    lib.graphlet_workspace_size.argtypes = [ctypes.POINTER(_Csr), ctypes.c_int, P]
+    lib.graphlet_workspace_size.restype = ctypes.c_size_t
+    lib.graphlet_count.argtypes = [ctypes.POINTER(_Csr), ctypes.POINTER(_U128), P, P,
+                                   ctypes.c_size_t, P, ctypes.c_uint32]
+    lib.graphlet_count.restype = ctypes.c_int
+    lib.graphlet_count_batched.argtypes = [ctypes.POINTER(_Batch), P, P, ctypes.c_uint32]
+    lib.graphlet_count_batched.restype = ctypes.c_int
+    lib.graphlet_last_error.argtypes = []
+    lib.graphlet_last_error.restype = ctypes.c_char_p
+    lib.graphlet_version.argtypes = []
+    lib.graphlet_version.restype = ctypes.c_char_p
+    lib.graphlet_timing_enable.argtypes = [ctypes.c_int]
+    lib.graphlet_timing_enable.restype = None
+    lib.graphlet_last_timing.argtypes = [ctypes.POINTER(_Timing)]
+    lib.graphlet_last_timing.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def graphlet_last_error() -> str:
+    return load().graphlet_last_error().decode()
+
+
+def _stream_ptr(stream=None) -> int:
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _check_dev(t, dtype, name):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _csr(row_ptr, col, n):
+    import torch
+
+    _check_dev(row_ptr, torch.int32, "row_ptr")
+    _check_dev(col, torch.int32, "col")
+    if row_ptr.numel() != n + 1:
+        raise ValueError("row_ptr must have n+1 entries")
+    return _Csr(int(n), int(col.numel()), row_ptr.data_ptr(), col.data_ptr() if col.numel() else 0)
+
+
+def graphlet_workspace_size(row_ptr, col, n: int, per_edge: bool = False, stream=None) -> int:
+    lib = load()
+    g = _csr(row_ptr, col, n)
+    size = lib.graphlet_workspace_size(ctypes.byref(g), int(per_edge), _stream_ptr(stream))
+    if size == 0:
+        raise GraphletError(-1, graphlet_last_error())
+    return int(size)
+
+
+def graphlet_count(row_ptr, col, n: int, per_edge: bool = False, workspace=None,
+                   validate: bool = False, stream=None, per_edge_out=None):
+    """17 exact counts (python ints) of one graph; with per_edge, also a
+    device int64 tensor [3, m] (|Tri_e|, 4-cliques, induced 4-cycles per
+    canonical edge)."""
+    import torch
+
+    lib = load()
+    g = _csr(row_ptr, col, n)
+    m = g.nnz // 2
+    pe = None
+    if per_edge:
+        if per_edge_out is not None:
+            _check_dev(per_edge_out, torch.int64, "per_edge_out")
+            if per_edge_out.numel() < 3 * m:
+                raise ValueError("per_edge_out too small")
+            pe = per_edge_out
+        else:
+            pe = torch.empty((3, max(m, 1)), dtype=torch.int64, device=row_ptr.device)
+    ws_ptr, ws_bytes = 0, 0
+    if workspace is not None:
+        _check_dev(workspace, torch.uint8, "workspace")
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel()
+    out = (_U128 * 17)()
+    rc = lib.graphlet_count(ctypes.byref(g), out, pe.data_ptr() if pe is not None else 0,
+                            ws_ptr, ws_bytes, _stream_ptr(stream),
+                            GC_VALIDATE if validate else 0)
+    if rc != 0:
+        raise GraphletError(rc, graphlet_last_error())
+    counts = [int(o.lo) | (int(o.hi) << 64) for o in out]
+    if per_edge:
+        return counts, pe[:, :m] if pe.dim() == 2 else pe
+    return counts
+
+
+def graphlet_count_batched(node_off, row_ptr, col, out=None, stream=None, validate=False):
+    """[G, 17] int64 device tensor of the counts of every graph of a batch."""
+    import torch
+
+    lib = load()
+    _check_dev(node_off, torch.int64, "node_off")
+    _check_dev(row_ptr, torch.int32, "row_ptr")
+    _check_dev(col, torch.int32, "col")
+    G = node_off.numel() - 1
+    if out is None:
+        out = torch.empty((max(G, 1), 17), dtype=torch.int64, device=node_off.device)
+    b = _Batch(G, node_off.data_ptr(), row_ptr.data_ptr(), col.data_ptr() if col.numel() else 0)
+    rc = lib.graphlet_count_batched(ctypes.byref(b), out.data_ptr(), _stream_ptr(stream),
+                                    GC_VALIDATE if validate else 0)
+    if rc != 0:
+        raise GraphletError(rc, graphlet_last_error())
+    return out[:G]
+
+
+def graphlet_timing_enable(on: bool = True) -> None:
+    """Record per-phase device times of this thread's graphlet_count calls."""
+    load().graphlet_timing_enable(1 if on else 0)
+
+
+def graphlet_last_timing() -> dict:
+    """Phase times (ms) and work counters of this thread's last graphlet_count."""
+    t = _Timing()
+    load().graphlet_last_timing(ctypes.byref(t))
+    d = {f"{p}_ms": float(t.ms[i]) for i, p in enumerate(PHASES)}
+    d.update(clique_entries=int(t.clique_entries), wedges_light=int(t.wedges_light),
+             wedges_heavy=int(t.wedges_heavy), heavy_items=int(t.heavy_items))
+    return d

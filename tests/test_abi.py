@@ -1,0 +1,56 @@
+"""The C-ABI library loads without a GPU and exports every declared symbol."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1506_04322_amd as gl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    with open(os.path.join(ROOT, "include", "graphlet.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(graphlet_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_exports():
+    assert declared_functions() == sorted(gl.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(gl.LIB_PATH):
+        pytest.skip("library not built")
+    lib = ctypes.CDLL(gl.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_version_and_error_without_gpu():
+    if not os.path.exists(gl.LIB_PATH):
+        pytest.skip("library not built")
+    lib = gl.load()
+    assert lib.graphlet_version().startswith(b"graphlet-mi355x")
+    assert gl.graphlet_last_error() == ""
+
+
+def test_null_arguments_are_rejected_without_touching_a_device():
+    if not os.path.exists(gl.LIB_PATH):
+        pytest.skip("library not built")
+    lib = gl.load()
+    assert lib.graphlet_count(None, None, None, None, 0, None, 0) == -1
+    assert "null" in gl.graphlet_last_error()
+    assert lib.graphlet_workspace_size(None, 0, None) == 0
+    bad = gl._Csr(5, 3, 0, 0)  # odd nnz
+    assert lib.graphlet_count(ctypes.byref(bad), (gl._U128 * 17)(), None, None, 0, None, 0) == -1
+    assert lib.graphlet_count_batched(None, None, None, 0) == -1
+
+
+def test_binding_fails_loudly_when_library_is_missing(tmp_path, monkeypatch):
+    monkeypatch.setattr(gl, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(gl, "_lib", None)
+    with pytest.raises(RuntimeError):
+        gl.load()

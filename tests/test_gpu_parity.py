@@ -1,0 +1,304 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+All counts are integers, so the bar is bit-exact equality everywhere: the
+17-vector (Table 1 classes) and the per-edge |Tri_e|, 4-clique and induced
+4-cycle counts in canonical edge order.
+"""
+import json
+import os
+from math import comb
+
+import numpy as np
+import pytest
+
+import graphgen
+import graphgen.configs as C
+import oracle
+import paper_1506_04322_amd as gl
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def gpu_counts(g, per_edge=False, validate=True):
+    rp = dev(g.row_ptr)
+    col = dev(g.col)
+    if per_edge:
+        c, pe = gl.graphlet_count(rp, col, g.n, per_edge=True, validate=validate)
+        return c, pe.cpu().numpy()
+    return gl.graphlet_count(rp, col, g.n, validate=validate)
+
+
+def check_full(g, route=oracle.identity_route, per_edge=True):
+    want = route(g)
+    got = gpu_counts(g)
+    assert got == want, (got, want)
+    if per_edge:
+        got2, pe = gpu_counts(g, per_edge=True)
+        assert got2 == want
+        eu, ev = oracle.edges(g)
+        if len(eu):
+            T, K4, C4 = oracle.per_edge(g, eu, ev)
+            np.testing.assert_array_equal(pe[0], T)
+            np.testing.assert_array_equal(pe[1], K4)
+            np.testing.assert_array_equal(pe[2], C4)
+
+
+def rand_graph(rng, n, p):
+    iu = np.triu_indices(n, 1)
+    mask = rng.random(len(iu[0])) < p
+    return graphgen.from_edges(n, list(zip(iu[0][mask], iu[1][mask])))
+
+
+# ------------------------------------------------------------ small graphs
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_small_graphs_vs_bruteforce(seed):
+    rng = np.random.default_rng(1000 + seed)
+    for _ in range(10):
+        n = int(rng.integers(0, 40))
+        g = rand_graph(rng, n, float(rng.random()))
+        check_full(g, route=oracle.bruteforce)
+
+
+def test_empty_and_tiny():
+    for n in range(0, 6):
+        g = graphgen.from_edges(n, [])
+        want = oracle.bruteforce(g)
+        assert gpu_counts(g) == want
+    g = graphgen.from_edges(3, [(0, 1)])
+    check_full(g, route=oracle.bruteforce)
+    g = graphgen.from_edges(2, [(0, 1)])
+    check_full(g, route=oracle.bruteforce)
+
+
+def test_isolated_vertices_many():
+    g = graphgen.from_edges(100000, [(0, 1), (1, 2), (2, 0), (5, 6), (99999, 3)])
+    check_full(g)
+
+
+def test_complete_graphs_cover_every_clique_bin():
+    # K_n: |U(u)| runs up to n-1, so n = 700 reaches the global-memory class
+    for n in (4, 65, 300, 700):
+        edges = [(a, b) for a in range(n) for b in range(a + 1, n)]
+        g = graphgen.from_edges(n, edges)
+        got, pe = gpu_counts(g, per_edge=True)
+        want = [0] * 17
+        want[0], want[2], want[6] = comb(n, 2), comb(n, 3), comb(n, 4)
+        assert got == want
+        assert (pe[0] == n - 2).all() and (pe[1] == comb(n - 2, 2)).all() and (pe[2] == 0).all()
+
+
+def test_complete_bipartite_heavy_cycles():
+    a, b = 300, 400
+    g = graphgen.from_edges(a + b, [(i, a + j) for i in range(a) for j in range(b)])
+    got, pe = gpu_counts(g, per_edge=True)
+    assert got == oracle.identity_route(g)
+    assert got[9] == comb(a, 2) * comb(b, 2)
+    assert (pe[0] == 0).all() and (pe[1] == 0).all() and (pe[2] == (a - 1) * (b - 1)).all()
+
+
+def test_star_and_hub_hub():
+    g = graphgen.from_edges(5001, [(0, i) for i in range(1, 5001)])
+    check_full(g)
+    rng = np.random.default_rng(5)
+    edges = [(0, 1)] + [(0, i) for i in range(2, 3000)] + [(1, i) for i in range(2, 3000, 2)]
+    edges += [tuple(rng.integers(2, 3000, 2)) for _ in range(4000)]
+    check_full(graphgen.from_edges(3000, edges))
+
+
+def test_dense_random_heavy_paths():
+    rng = np.random.default_rng(9)
+    check_full(rand_graph(rng, 400, 0.35))
+    check_full(rand_graph(rng, 900, 0.05))
+
+
+def test_powerlaw_and_rmat_medium():
+    check_full(graphgen.chung_lu(20000, 2.1, 4.0, 120000, 11))
+    check_full(graphgen.rmat(13, 16, 0.57, 0.19, 0.19, 12))
+
+
+def test_rgg_and_er_medium():
+    check_full(graphgen.rgg_torus(3000, 12.0, 13))
+    check_full(graphgen.er_gnm(5000, 60000, 14))
+
+
+def test_run_to_run_identical_and_relabelled():
+    g = graphgen.rmat(12, 16, 0.57, 0.19, 0.19, 21)
+    a = gpu_counts(g, per_edge=True)
+    b = gpu_counts(g, per_edge=True)
+    assert a[0] == b[0] and (a[1] == b[1]).all()
+    perm = np.random.default_rng(3).permutation(g.n)
+    eu, ev = oracle.edges(g)
+    h = graphgen.from_edges(g.n, list(zip(perm[eu], perm[ev])))
+    assert gpu_counts(h) == a[0]
+
+
+# ------------------------------------------------------------ configurations
+
+
+def golden(name):
+    path = os.path.join(HERE, "golden", "configs.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f).get(name)
+    return d
+
+
+def test_config1_er_full():
+    g = C.er()
+    gd = golden("er")
+    assert gd is not None and gd["sha256"] == g.sha256()
+    want = [int(x) for x in gd["counts"]]
+    assert want == oracle.identity_route(g)
+    check_full(g)
+
+
+def _sampled_edges(g, k, seed):
+    eu, ev = oracle.edges(g)
+    rng = np.random.default_rng(seed)
+    idx = np.unique(np.concatenate([rng.integers(0, len(eu), k), np.arange(min(50, len(eu)))]))
+    # also the edges at the highest-degree vertex
+    d = g.degrees()
+    hub = int(np.argmax(d))
+    hub_idx = np.nonzero((eu == hub) | (ev == hub))[0][:50]
+    idx = np.unique(np.concatenate([idx, hub_idx]))
+    return idx, eu[idx], ev[idx]
+
+
+def test_config2_chung_lu_full_size():
+    g = C.cl()
+    got, pe = gpu_counts(g, per_edge=True, validate=False)
+    assert got == gpu_counts(g, validate=False)
+    gd = golden("cl")
+    if gd is not None:
+        assert gd["sha256"] == g.sha256()
+        assert got == [int(x) for x in gd["counts"]]
+    idx, eu, ev = _sampled_edges(g, 3000, 22)
+    T, K4, C4 = oracle.per_edge(g, eu, ev)
+    np.testing.assert_array_equal(pe[0][idx], T)
+    np.testing.assert_array_equal(pe[1][idx], K4)
+    np.testing.assert_array_equal(pe[2][idx], C4)
+    # sum rules that hold at any size
+    assert int(pe[0].sum()) == 3 * got[2]
+    assert int(pe[1].sum()) == 6 * got[6]
+    assert int(pe[2].sum()) == 4 * got[9]
+    assert sum(got[2:6]) == comb(g.n, 3) and sum(got[6:]) == comb(g.n, 4)
+
+
+def test_config3_rmat22_full_size():
+    gd = golden("rmat")
+    if gd is None:
+        pytest.skip("R-MAT oracle counts not generated yet")
+    g = C.rmat22()
+    assert gd["sha256"] == g.sha256()
+    got = gpu_counts(g, validate=False)
+    assert got == [int(x) for x in gd["counts"]]
+    assert got[5] > 2**63  # needs the 128-bit path
+
+
+# ------------------------------------------------------------ API behaviour
+
+
+def test_validation_rejects_bad_csr():
+    import torch
+
+    def call(n, rp, col):
+        with pytest.raises(gl.GraphletError) as e:
+            gl.graphlet_count(dev(np.array(rp, np.int32)), dev(np.array(col, np.int32)), n,
+                              validate=True)
+        return e.value.code
+
+    assert call(3, [0, 2, 3, 4], [2, 1, 0, 0]) == -2  # unsorted row 0
+    assert call(2, [0, 2, 4], [0, 1, 0, 1]) == -3  # self loops, symmetric
+    assert call(3, [0, 1, 1, 2], [1, 0]) == -4  # 0->1 but 1 has no list entry
+    assert call(2, [0, 1, 2], [5, 0]) == -4  # id out of range
+    torch.cuda.synchronize()
+
+
+def test_explicit_workspace():
+    import torch
+
+    g = graphgen.er_gnm(1000, 8000, 31)
+    rp, col = dev(g.row_ptr), dev(g.col)
+    need = gl.graphlet_workspace_size(rp, col, g.n, per_edge=True)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda:0")
+    c, pe = gl.graphlet_count(rp, col, g.n, per_edge=True, workspace=ws)
+    assert c == oracle.identity_route(g)
+    small = torch.empty(need // 2, dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(gl.GraphletError) as e:
+        gl.graphlet_count(rp, col, g.n, per_edge=True, workspace=small)
+    assert e.value.code == -6
+
+
+# ------------------------------------------------------------ batched
+
+
+def batched_gpu(b):
+    out = gl.graphlet_count_batched(dev(b.node_off), dev(b.row_ptr), dev(b.col))
+    return out.cpu().numpy()
+
+
+def make_batch(graphs):
+    node_off = [0]
+    rp = [0]
+    cols = []
+    for g in graphs:
+        base = rp[-1]
+        rp.extend((base + g.row_ptr[1:]).tolist())
+        cols.append(g.col)
+        node_off.append(node_off[-1] + g.n)
+    col = np.concatenate(cols) if cols else np.zeros(0, np.int32)
+    return graphgen.Batch(np.array(node_off, np.int64), np.zeros(len(graphs), np.int64),
+                          np.array(rp, np.int32), col.astype(np.int32))
+
+
+def test_batched_mixed_sizes_vs_oracle():
+    rng = np.random.default_rng(77)
+    graphs = []
+    for n in [0, 1, 2, 3, 4, 5, 17, 64, 65, 200, 256, 257, 400, 640, 641, 800, 1024]:
+        graphs.append(rand_graph(rng, n, float(rng.uniform(0.02, 0.3))))
+    graphs.append(graphgen.rgg_torus(500, 8.0, 3))
+    graphs.append(graphgen.from_edges(30, [(a, b) for a in range(30) for b in range(a + 1, 30)]))
+    b = make_batch(graphs)
+    out = batched_gpu(b)
+    for i, g in enumerate(graphs):
+        assert out[i].tolist() == oracle.identity_route(g), i
+
+
+def test_batched_config4_sample():
+    b = C.batch8192()
+    out = batched_gpu(b)
+    rng = np.random.default_rng(4)
+    for i in rng.choice(b.graphs, 120, replace=False):
+        g = b.graph(int(i))
+        assert out[i].tolist() == oracle.identity_route(g), i
+    # every row is a complete census of its graph
+    n = np.diff(b.node_off)
+    assert (out[:, 2:6].sum(1) == n * (n - 1) * (n - 2) // 6).all()
+    assert (out[:, 6:].sum(1) == n * (n - 1) * (n - 2) * (n - 3) // 24).all()
+
+
+def test_batched_equals_single_graph_path():
+    b = C.batch8192(64)
+    out = batched_gpu(b)
+    for i in range(b.graphs):
+        g = b.graph(i)
+        assert out[i].tolist() == gpu_counts(g, validate=False)
+
+
+def test_batched_rejects_oversized_graph():
+    g = graphgen.from_edges(1100, [(0, 1)])
+    b = make_batch([g])
+    with pytest.raises(gl.GraphletError) as e:
+        batched_gpu(b)
+    assert e.value.code == -5
