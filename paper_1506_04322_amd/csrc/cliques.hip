@@ -1,0 +1,313 @@
+// Steps 1 and 2a: |Tri_e| of every edge and the 4-cliques.
+//
+// One workgroup per vertex u with k = |U(u)| >= 2 upper neighbours (in the
+// degree order).  The subgraph induced by U(u) is built in LDS as a bitmap:
+// bit (i, j) means U_j is in U(U_i), i.e. {u, U_i, U_j} is a triangle whose
+// lowest vertex is u.  Each triangle is therefore found exactly once, which
+// replaces the marking array X of the paper's triad census (Section 3) by a
+// per-vertex bitmap:
+//   * |Tri| of edge (U_i, U_j) gains one (global atomic at its position);
+//   * |Tri| of edge (u, U_i) is the number of local neighbours of U_i;
+//   * the 4-cliques with lowest vertex u are the triangles of the local
+//     graph: AND + popcount of two rows (CliqueCount of Section 4.4, which
+//     marks Tri_e and scans neighbour lists, reads the same adjacencies).
+//
+// Global mode keeps only the upper half of the local adjacency (bit j > i in
+// row i), packed triangularly; a column counter per local vertex gives the
+// lower half's contribution to |Tri|.  U(u) is indexed by an LDS hash.
+// Per-edge mode keeps symmetric rows, so that every local edge can read its
+// common-neighbour count (4-cliques through that edge).
+#include <algorithm>
+
+#include "kernels.h"
+
+namespace gc {
+
+namespace {
+
+// Exclusive scan of A[0..k) in place; total in A[k].  BLOCK threads.
+template <int BLOCK>
+__device__ void block_scan_excl(int32_t *A, int k, int32_t *sums) {
+  const int tid = threadIdx.x;
+  const int per = (k + BLOCK - 1) / BLOCK;
+  const int a = min(k, tid * per), b = min(k, a + per);
+  int32_t s = 0;
+  for (int i = a; i < b; i++) s += A[i];
+  sums[tid] = s;
+  __syncthreads();
+  for (int off = 1; off < BLOCK; off <<= 1) {
+    const int32_t t = tid >= off ? sums[tid - off] : 0;
+    __syncthreads();
+    sums[tid] += t;
+    __syncthreads();
+  }
+  int32_t run = sums[tid] - s;
+  for (int i = a; i < b; i++) {
+    const int32_t v = A[i];
+    A[i] = run;
+    run += v;
+  }
+  if (tid == BLOCK - 1) A[k] = sums[BLOCK - 1];
+  __syncthreads();
+}
+
+__device__ __forceinline__ uint32_t hslot(int32_t x, int hbits) {
+  return ((uint32_t)x * 2654435761u) >> (32 - hbits);
+}
+
+// Local index of vertex x in U(u), or -1.  H holds index + 1 (0 = empty).
+__device__ __forceinline__ int hfind(const int32_t *H, const int32_t *U, uint32_t mask, int hbits,
+                                     int32_t x) {
+  uint32_t h = hslot(x, hbits);
+  while (true) {
+    const int v = H[h];
+    if (v == 0) return -1;
+    if (U[v - 1] == x) return v - 1;
+    h = (h + 1) & mask;
+  }
+}
+
+// Row i of the triangular layout holds words [i >> 6, W) of the upper half.
+__device__ __forceinline__ int tri_off(int i, int W) {
+  const int q = i >> 6;
+  return i * W - (32 * q * (q - 1) + q * (i - 64 * q));
+}
+
+// ------------------------------------------------------------ global mode
+
+template <int BLOCK, int KCAP, int HS>
+__global__ __launch_bounds__(BLOCK) void k_tk_up(TkArgs g) {
+  constexpr int WC = (KCAP + 63) / 64;
+  constexpr int RWORDS = 32 * WC * (WC + 1);  // tri_off(64 WC, WC)
+  constexpr int RUN = 4;                       // consecutive entries per thread
+  __shared__ int32_t U[KCAP], V[KCAP], P[KCAP + 1], H[HS], sums[BLOCK];
+  __shared__ uint32_t colcnt[KCAP];
+  __shared__ u64 R[RWORDS];
+  __shared__ u64 red[32];
+  __shared__ int next;
+  const int tid = threadIdx.x;
+  u128 k4acc = 0;
+  for (int it = blockIdx.x; it < g.nlist; it += gridDim.x) {
+    const int u = g.list[it];
+    const int k = g.ucnt[u];
+    const int base = g.ustart[u];
+    const int W = (k + 63) >> 6;
+    int hs = 64;
+    while (hs < 2 * k) hs <<= 1;
+    const int hbits = __ffs(hs) - 1;
+    const uint32_t mask = (uint32_t)hs - 1;
+    const int rwords = tri_off(k, W);
+    for (int i = tid; i < k; i += BLOCK) {
+      U[i] = g.col2[base + i];
+      colcnt[i] = 0;
+    }
+    for (int h = tid; h < hs; h += BLOCK) H[h] = 0;
+    for (int w = tid; w < rwords; w += BLOCK) R[w] = 0;
+    if (tid == 0) next = 0;
+    __syncthreads();
+    for (int i = tid; i < k; i += BLOCK) {
+      const int v = U[i];
+      V[i] = g.ustart[v];
+      P[i] = g.ucnt[v];
+      uint32_t h = hslot(v, hbits);
+      while (atomicCAS(&H[h], 0, i + 1) != 0) h = (h + 1) & mask;
+    }
+    __syncthreads();
+    block_scan_excl<BLOCK>(P, k, sums);
+    const int total = P[k];
+    // Build: every entry x of U(U_i) that lies in U(u) is a triangle.
+    for (int t0 = tid * RUN; t0 < total; t0 += BLOCK * RUN) {
+      int i = upper_index_dev<int32_t>(P, k, t0);
+      const int t1 = min(t0 + RUN, total);
+      for (int t = t0; t < t1; t++) {
+        while (P[i + 1] <= t) i++;
+        const int pos = V[i] + (t - P[i]);
+        const int j = hfind(H, U, mask, hbits, g.col2[pos]);
+        if (j >= 0) {
+          atomicOr(&R[tri_off(i, W) + (j >> 6) - (i >> 6)], 1ull << (j & 63));
+          atomicAdd(&colcnt[j], 1u);
+          atomicAdd(&g.T[pos], 1u);
+        }
+      }
+    }
+    __syncthreads();
+    // |Tri| of edges (u, U_i); 4-cliques u < U_i < U_j < U_l, each once.
+    u64 acc = 0;
+    for (int i = atomicAdd(&next, 1); i < k; i = atomicAdd(&next, 1)) {
+      const u64 *Ri = R + tri_off(i, W);
+      const int qi = i >> 6;
+      uint32_t c = colcnt[i];
+      for (int w = qi; w < W; w++) c += (uint32_t)__popcll(Ri[w - qi]);
+      if (c) atomicAdd(&g.T[base + i], c);
+      for (int w = qi; w < W; w++) {
+        u64 bits = Ri[w - qi];
+        while (bits) {
+          const int j = (w << 6) + __ffsll((long long)bits) - 1;
+          bits &= bits - 1;
+          const u64 *Rj = R + tri_off(j, W);
+          const int qj = j >> 6;
+          for (int z = qj; z < W; z++) acc += (u64)__popcll(Ri[z - qi] & Rj[z - qj]);
+        }
+      }
+    }
+    k4acc += (u128)acc;
+    __syncthreads();
+  }
+  const u128 s = block_sum_u128(k4acc, red);
+  if (threadIdx.x == 0 && s) atomic_add_u128(g.k4, s);
+}
+
+// ------------------------------------------------------------ symmetric rows
+
+template <int BLOCK, bool PER_EDGE>
+__device__ void tk_vertex(const TkArgs &g, int u, int32_t *U, int32_t *V, int32_t *P, u64 *R,
+                          int words, int32_t *sums, u64 *A1, u64 *A2, uint32_t *Tu,
+                          u128 &k4acc) {
+  const int tid = threadIdx.x;
+  const int k = g.ucnt[u];
+  const int base = g.ustart[u];
+  for (int i = tid; i < k; i += BLOCK) U[i] = g.col2[base + i];
+  for (int w = tid; w < k * words; w += BLOCK) R[w] = 0;
+  __syncthreads();
+  for (int i = tid; i < k; i += BLOCK) {
+    const int v = U[i];
+    V[i] = g.ustart[v];
+    P[i] = g.ucnt[v];
+    if (PER_EDGE) {
+      Tu[i] = g.T[base + i];
+      A1[i] = 0;
+      A2[i] = 0;
+    }
+  }
+  __syncthreads();
+  block_scan_excl<BLOCK>(P, k, sums);
+  const int total = P[k];
+  for (int t = tid; t < total; t += BLOCK) {
+    const int i = upper_index_dev<int32_t>(P, k, t);
+    const int pos = V[i] + (t - P[i]);
+    const int x = g.col2[pos];
+    const int j = i + 1 + lower_bound_dev<int32_t>(U + i + 1, k - i - 1, x);
+    if (j < k && U[j] == x) {
+      atomicOr(&R[(size_t)i * words + (j >> 6)], 1ull << (j & 63));
+      atomicOr(&R[(size_t)j * words + (i >> 6)], 1ull << (i & 63));
+      if (!PER_EDGE) atomicAdd(&g.T[pos], 1u);
+    }
+  }
+  __syncthreads();
+  if (!PER_EDGE) {
+    u64 acc = 0;
+    for (int i = tid; i < k; i += BLOCK) {
+      const u64 *Ri = R + (size_t)i * words;
+      uint32_t c = 0;
+      for (int w = 0; w < words; w++) c += (uint32_t)__popcll(Ri[w]);
+      if (c) atomicAdd(&g.T[base + i], c);
+      for (int w = (i + 1) >> 6; w < words; w++) {
+        u64 bits = Ri[w];
+        if (w == ((i + 1) >> 6)) bits &= (~0ull) << ((i + 1) & 63);
+        while (bits) {
+          const int j = (w << 6) + __ffsll((long long)bits) - 1;
+          bits &= bits - 1;
+          const u64 *Rj = R + (size_t)j * words;
+          for (int z = 0; z < words; z++) acc += (u64)__popcll(Ri[z] & Rj[z]);
+        }
+      }
+    }
+    k4acc += (u128)acc;
+  } else {
+    // Per local edge (i, j): 4-cliques {u, U_i, U_j, x}, x in U(u), and the
+    // D_e terms of the 4-cycle identity (|Tri| is final here).
+    for (int t = tid; t < total; t += BLOCK) {
+      const int i = upper_index_dev<int32_t>(P, k, t);
+      const int pos = V[i] + (t - P[i]);
+      const int x = g.col2[pos];
+      const int j = i + 1 + lower_bound_dev<int32_t>(U + i + 1, k - i - 1, x);
+      if (j < k && U[j] == x) {
+        const u64 *Ri = R + (size_t)i * words, *Rj = R + (size_t)j * words;
+        u64 c = 0;
+        for (int z = 0; z < words; z++) c += (u64)__popcll(Ri[z] & Rj[z]);
+        const u64 tij = g.T[pos];
+        if (c) atomicAdd(&g.K4w[pos], c);
+        atomicAdd(&g.Dw[pos], (u64)Tu[i] + Tu[j] - 2);
+        if (c) {
+          atomicAdd(&A1[i], c);
+          atomicAdd(&A1[j], c);
+        }
+        atomicAdd(&A2[i], (u64)Tu[j] + tij - 2);
+        atomicAdd(&A2[j], (u64)Tu[i] + tij - 2);
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < k; i += BLOCK) {
+      if (A1[i]) atomicAdd(&g.K4w[base + i], A1[i] / 2);
+      if (A2[i]) atomicAdd(&g.Dw[base + i], A2[i]);
+    }
+  }
+  __syncthreads();
+}
+
+template <int BLOCK, int KMAX>
+__global__ __launch_bounds__(BLOCK) void k_tk_lds_pe(TkArgs g) {
+  constexpr int WORDS = (KMAX + 63) / 64;
+  __shared__ int32_t U[KMAX], V[KMAX], P[KMAX + 1], sums[BLOCK];
+  __shared__ u64 R[KMAX * WORDS];
+  __shared__ u64 A1[KMAX], A2[KMAX];
+  __shared__ uint32_t Tu[KMAX];
+  u128 unused = 0;
+  for (int it = blockIdx.x; it < g.nlist; it += gridDim.x) {
+    const int u = g.list[it];
+    const int words = (g.ucnt[u] + 63) / 64;
+    tk_vertex<BLOCK, true>(g, u, U, V, P, R, words, sums, A1, A2, Tu, unused);
+  }
+}
+
+// Fallback for large k: rows and arrays in global memory, one slot per block.
+template <int BLOCK, bool PER_EDGE>
+__global__ __launch_bounds__(BLOCK) void k_tk_global(TkArgs g) {
+  __shared__ int32_t sums[BLOCK];
+  __shared__ u64 red[32];
+  const size_t kmax = (size_t)g.kmax;
+  const size_t wmax = (kmax + 63) / 64;
+  u64 *R = g.gR + (size_t)blockIdx.x * kmax * wmax;
+  int32_t *I = g.gI + (size_t)blockIdx.x * (3 * kmax + 1);
+  int32_t *U = I, *V = I + kmax, *P = I + 2 * kmax;
+  u64 *A1 = g.gA + (size_t)blockIdx.x * 3 * kmax;
+  u64 *A2 = A1 + kmax;
+  uint32_t *Tu = reinterpret_cast<uint32_t *>(A2 + kmax);
+  u128 k4acc = 0;
+  for (int it = blockIdx.x; it < g.nlist; it += gridDim.x) {
+    const int u = g.list[it];
+    const int words = (g.ucnt[u] + 63) / 64;
+    tk_vertex<BLOCK, PER_EDGE>(g, u, U, V, P, R, words, sums, A1, A2, Tu, k4acc);
+  }
+  if (!PER_EDGE) {
+    const u128 s = block_sum_u128(k4acc, red);
+    if (threadIdx.x == 0 && s) atomic_add_u128(g.k4x3, s);
+  }
+}
+
+}  // namespace
+
+int launch_cliques(TkArgs g, int bin, bool per_edge, hipStream_t s) {
+  if (g.nlist <= 0) return GC_OK;
+  auto grid = [&](int cap) { return (unsigned)std::min(g.nlist, cap); };
+  if (!per_edge) {
+    switch (bin) {
+      case 0: k_tk_up<64, kTkLim0, 128><<<grid(65536), 64, 0, s>>>(g); break;
+      case 1: k_tk_up<256, kTkLim1, 512><<<grid(16384), 256, 0, s>>>(g); break;
+      case 2: k_tk_up<256, kTkLim2, 1024><<<grid(8192), 256, 0, s>>>(g); break;
+      case 3: k_tk_up<512, kTkLim3, 4096><<<grid(4096), 512, 0, s>>>(g); break;
+      default: k_tk_global<256, false><<<grid(kTkGlobalSlots), 256, 0, s>>>(g); break;
+    }
+  } else {
+    switch (bin) {
+      case 0: k_tk_lds_pe<64, kTkLim0><<<grid(65536), 64, 0, s>>>(g); break;
+      case 1: k_tk_lds_pe<256, kTkLim1><<<grid(16384), 256, 0, s>>>(g); break;
+      case 2: k_tk_lds_pe<256, kTkLim2><<<grid(4096), 256, 0, s>>>(g); break;
+      default: k_tk_global<256, true><<<grid(kTkGlobalSlots), 256, 0, s>>>(g); break;
+    }
+  }
+  GC_TRY_HIP(hipGetLastError());
+  return GC_OK;
+}
+
+}  // namespace gc

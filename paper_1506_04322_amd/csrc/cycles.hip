@@ -1,0 +1,241 @@
+// Step 2b: 4-cycles through every edge.
+//
+// The paper's CycleCount (Section 4.4) marks Star_v and scans N(w) for every
+// w in Star_u: O(|E| Delta S_max) reads, about 1.5e14 on R-MAT scale 22.
+// Here the same per-edge numbers come from
+//     C4_e = C4ni_e - D_e + 2 K4_e,
+// where C4ni_e counts the 4-cycles through e whether or not they have chords,
+// D_e = sum_{w in Tri_e} (|Tri_(u,w)| + |Tri_(v,w)| - 2) counts the chorded
+// ones through each chord-carrying triangle vertex, and the 4-cycles with both
+// chords (4-cliques) are subtracted twice by D_e, hence + 2 K4_e.  C4ni comes
+// from wedge aggregation: a 4-cycle has one highest vertex x (degree order)
+// and is the union of two paths x - v - y with v, y below x, so with c(x, y)
+// the number of such paths, the cycles through x as highest vertex are
+// C(c(x, y), 2) per y.  In the per-edge pass, each wedge x - v - y lies on
+// c(x, y) - 1 cycles, credited to its two edges.
+//
+// Light x (few wedges): one wavefront, c(x, .) in an LDS hash.
+// Heavy x: work items (x, y range); the range is walked in chunks of LDS
+// counters, and every lower neighbour v of x keeps a cursor into its sorted
+// list, so each wedge entry is read once per pass.
+#include <algorithm>
+
+#include "kernels.h"
+
+namespace gc {
+
+namespace {
+
+__device__ __forceinline__ u64 choose2(u64 c) { return c * (c - 1) / 2; }
+
+// Upper position of the undirected edge stored at position p of N(v).
+__device__ __forceinline__ int upper_pos(const int32_t *col2, const int32_t *tpos, int p, int v) {
+  return col2[p] > v ? p : tpos[p];
+}
+
+template <bool PER_EDGE>
+__global__ __launch_bounds__(kWave) void k_c4_light(C4Args g) {
+  __shared__ int32_t hkey[kHashSlots];
+  __shared__ uint32_t hcnt[kHashSlots];
+  __shared__ int32_t sIncl[kWave], sStart[kWave], sLen[kWave], sQ[kWave], sV[kWave];
+  __shared__ u64 red[32];
+  const int lane = threadIdx.x;
+  for (int h = lane; h < kHashSlots; h += kWave) {
+    hkey[h] = -1;
+    hcnt[h] = 0;
+  }
+  __syncthreads();
+  u128 acc = 0;
+  for (int it = blockIdx.x; it < g.nlist; it += gridDim.x) {
+    const int x = g.list[it];
+    const u64 w = g.W[x];
+    int hs = 64;
+    while ((u64)hs < 2 * w) hs <<= 1;
+    const uint32_t mask = (uint32_t)hs - 1;
+    const int hbits = __ffs(hs) - 1;
+    const int Lx = g.rp2[x], nL = g.lcnt[x];
+    for (int pass = 0; pass < (PER_EDGE ? 2 : 1); pass++) {
+      for (int b = 0; b < nL; b += kWave) {
+        const int i = b + lane;
+        int len = 0;
+        if (i < nL) {
+          const int q = Lx + i;
+          const int v = g.col2[q];
+          const int s = g.rp2[v];
+          len = g.tpos[q] - s;
+          sStart[lane] = s;
+          sQ[lane] = q;
+          sV[lane] = v;
+        }
+        int incl = len;
+        for (int off = 1; off < kWave; off <<= 1) {
+          const int t = __shfl_up(incl, off, kWave);
+          if (lane >= off) incl += t;
+        }
+        sIncl[lane] = incl;
+        sLen[lane] = len;
+        __syncthreads();
+        const int total = sIncl[kWave - 1];
+        for (int t = lane; t < total; t += kWave) {
+          int lo = 0, hi = kWave - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (sIncl[mid] > t) hi = mid;
+            else lo = mid + 1;
+          }
+          const int p = sStart[lo] + (t - (sIncl[lo] - sLen[lo]));
+          const int y = g.col2[p];
+          uint32_t h = ((uint32_t)y * 2654435761u) >> (32 - hbits);
+          if (pass == 0) {
+            while (true) {
+              const int old = atomicCAS(&hkey[h], -1, y);
+              if (old == -1 || old == y) {
+                atomicAdd(&hcnt[h], 1u);
+                break;
+              }
+              h = (h + 1) & mask;
+            }
+          } else {
+            while (hkey[h] != y) h = (h + 1) & mask;
+            const u64 c = hcnt[h];
+            if (c >= 2) {
+              atomicAdd(&g.C4w[upper_pos(g.col2, g.tpos, p, sV[lo])], c - 1);
+              atomicAdd(&g.C4w[g.tpos[sQ[lo]]], c - 1);
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int h = lane; h < hs; h += kWave) {
+      if (hkey[h] != -1) {
+        acc += (u128)choose2(hcnt[h]);
+        hkey[h] = -1;
+        hcnt[h] = 0;
+      }
+    }
+    __syncthreads();
+  }
+  const u128 s = block_sum_u128(acc, red);
+  if (threadIdx.x == 0 && s) atomic_add_u128(g.c4ni, s);
+}
+
+template <bool PER_EDGE>
+__global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy(C4Args g) {
+  __shared__ uint32_t cnt[kChunkWords];
+  __shared__ u64 red[32];
+  __shared__ int s_item;
+  const int tid = threadIdx.x;
+  const int64_t nitems = *g.nitems;
+  int32_t *cur = g.gcur + (size_t)blockIdx.x * g.lmax;
+  int32_t *beg = PER_EDGE ? g.gbeg + (size_t)blockIdx.x * g.lmax : nullptr;
+  u64 *cacc = PER_EDGE ? g.gacc + (size_t)blockIdx.x * g.lmax : nullptr;
+  u128 acc = 0;
+  while (true) {
+    if (tid == 0) s_item = (int)atomicAdd(g.queue, 1ull);
+    __syncthreads();
+    const int item = s_item;
+    __syncthreads();
+    if (item >= nitems) break;
+    const int4 it = g.items[item];
+    const int x = it.x, ya = it.y, yb = it.z;
+    const int Lx = g.rp2[x], nL = g.lcnt[x];
+    // 2 x 16-bit counters per word while no count can reach 2^16
+    const bool packed = nL < 65536;
+    const int K = packed ? 2 * kChunkWords : kChunkWords;
+    for (int i = tid; i < nL; i += kC4HeavyBlock) {
+      const int q = Lx + i;
+      const int s = g.rp2[g.col2[q]];
+      const int e = g.tpos[q];
+      cur[i] = s + lower_bound_dev<int32_t>(g.col2 + s, e - s, ya);
+      if (PER_EDGE) cacc[i] = 0;
+    }
+    __syncthreads();
+    for (int c0 = ya; c0 < yb; c0 += K) {
+      const int c1 = min(c0 + K, yb);
+      for (int w = tid; w < kChunkWords; w += kC4HeavyBlock) cnt[w] = 0;
+      __syncthreads();
+      for (int i = tid; i < nL; i += kC4HeavyBlock) {
+        const int e = g.tpos[Lx + i];
+        int p = cur[i];
+        if (PER_EDGE) beg[i] = p;
+        // four independent loads per round keep more requests in flight
+        while (p < e) {
+          const int y0 = g.col2[p];
+          const int y1 = p + 1 < e ? g.col2[p + 1] : INT32_MAX;
+          const int y2 = p + 2 < e ? g.col2[p + 2] : INT32_MAX;
+          const int y3 = p + 3 < e ? g.col2[p + 3] : INT32_MAX;
+          int ys[4] = {y0, y1, y2, y3};
+          bool stop = false;
+#pragma unroll
+          for (int r = 0; r < 4; r++) {
+            const int y = ys[r];
+            if (y >= c1) {
+              stop = true;
+              break;
+            }
+            const int d = y - c0;
+            if (packed) atomicAdd(&cnt[d >> 1], (d & 1) ? 65536u : 1u);
+            else atomicAdd(&cnt[d], 1u);
+            p++;
+          }
+          if (stop) break;
+        }
+        cur[i] = p;
+      }
+      __syncthreads();
+      if (PER_EDGE) {
+        for (int i = tid; i < nL; i += kC4HeavyBlock) {
+          const int v = g.col2[Lx + i];
+          u64 credit = 0;
+          for (int p = beg[i]; p < cur[i]; p++) {
+            const int d = g.col2[p] - c0;
+            const u64 c = packed ? ((cnt[d >> 1] >> ((d & 1) * 16)) & 0xffffu) : cnt[d];
+            if (c >= 2) {
+              atomicAdd(&g.C4w[upper_pos(g.col2, g.tpos, p, v)], c - 1);
+              credit += c - 1;
+            }
+          }
+          cacc[i] += credit;
+        }
+        __syncthreads();
+      }
+      u64 part = 0;
+      for (int w = tid; w < kChunkWords; w += kC4HeavyBlock) {
+        const uint32_t val = cnt[w];
+        if (packed) part += choose2(val & 0xffffu) + choose2(val >> 16);
+        else part += choose2(val);
+      }
+      acc += (u128)part;
+      __syncthreads();
+    }
+    if (PER_EDGE) {
+      for (int i = tid; i < nL; i += kC4HeavyBlock)
+        if (cacc[i]) atomicAdd(&g.C4w[g.tpos[Lx + i]], cacc[i]);
+    }
+    __syncthreads();
+  }
+  const u128 s = block_sum_u128(acc, red);
+  if (threadIdx.x == 0 && s) atomic_add_u128(g.c4ni, s);
+}
+
+}  // namespace
+
+int launch_cycles_light(C4Args g, bool per_edge, hipStream_t s) {
+  if (g.nlist <= 0) return GC_OK;
+  const unsigned grid = (unsigned)std::min(g.nlist, 65536);
+  if (per_edge) k_c4_light<true><<<grid, kWave, 0, s>>>(g);
+  else k_c4_light<false><<<grid, kWave, 0, s>>>(g);
+  GC_TRY_HIP(hipGetLastError());
+  return GC_OK;
+}
+
+int launch_cycles_heavy(C4Args g, int slots, bool per_edge, hipStream_t s) {
+  if (slots <= 0) return GC_OK;
+  if (per_edge) k_c4_heavy<true><<<slots, kC4HeavyBlock, 0, s>>>(g);
+  else k_c4_heavy<false><<<slots, kC4HeavyBlock, 0, s>>>(g);
+  GC_TRY_HIP(hipGetLastError());
+  return GC_OK;
+}
+
+}  // namespace gc

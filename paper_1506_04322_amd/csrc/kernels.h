@@ -1,0 +1,184 @@
+// Internal interfaces between the host pipeline and the kernel files of the
+// single-graph path (not part of the ABI).
+#pragma once
+
+#include "common.h"
+
+namespace gc {
+
+// ---------------------------------------------------------------- constants
+
+// Step-3 accumulators (unrestricted counts of Section 4.2, summed over edges).
+constexpr int kAcc = 13;
+enum AccIdx {
+  A_T = 0,  // sum |Tri_e|
+  A_S,      // sum |Star_u| + |Star_v|
+  A_I,      // sum I_e = |V| - |N(u) u N(v)|
+  A_TT,     // sum C(T, 2)                      N_{T,T}
+  A_SUSV,   // sum Su Sv                        N_{Su,Sv}
+  A_TS,     // sum T (Su + Sv)                  N_{T,Su v Sv}
+  A_SS,     // sum C(Su,2) + C(Sv,2)            N_{S.,S.}
+  A_TI,     // sum T I                          N_{T,I}
+  A_SI,     // sum (Su + Sv) I                  N_{Su v Sv,I}
+  A_II,     // sum C(I, 2)                      N_{I,I}
+  A_II1,    // sum |E| - d_u - d_v + 1           (N_{I,I,1} before its subtractions)
+  A_K4,     // sum 4-cliques through e           N_{T,T,1}
+  A_C4      // sum induced 4-cycles through e    N_{Su,Sv,1}
+};
+
+// Size classes of the clique pass by k = |U(u)|.
+constexpr int kTkBins = 5;
+constexpr int kTkLim0 = 64, kTkLim1 = 256, kTkLim2 = 512, kTkLim3 = 1088;
+// Class of a vertex with k = |U(u)| >= 2 upper neighbours.
+__host__ __device__ inline int tk_class(int k) {
+  return k <= kTkLim0 ? 0 : k <= kTkLim1 ? 1 : k <= kTkLim2 ? 2 : k <= kTkLim3 ? 3 : 4;
+}
+// Light wedge vertices: at most this many wedges (LDS hash of <= 2048 slots).
+constexpr u64 kLightWedges = 1024;
+constexpr int kHashSlots = 2048;
+// Heavy wedge vertices: LDS counter chunk of 128 KiB.
+constexpr int kChunkWords = 32768;
+constexpr int kC4HeavyBlock = 1024;
+// Target wedges per heavy work item.
+constexpr u64 kPieceWork = u64(1) << 21;
+// Concurrent workgroups of the global-memory clique kernel.
+constexpr int kTkGlobalSlots = 256;
+
+// Device accumulators and scalars (u64 words; filled with zero per call).
+struct DevAcc {
+  u64 k4;       // number of 4-cliques (global mode)
+  u64 k4_hi;
+  u64 k4x3;     // 3 x 4-cliques (fallback kernel counts each clique 3 times)
+  u64 k4x3_hi;
+  u64 c4ni;     // number of 4-cycles, chords allowed
+  u64 c4ni_hi;
+  u64 step3[kAcc][2];
+  int32_t err;  // contract violations (bit -code per kind)
+  int32_t pad;
+  u64 queue;    // persistent work-queue heads
+  u64 queue2;
+  int64_t nitems;  // heavy wedge work items
+};
+
+struct Counters {
+  int32_t tk_cnt[kTkBins];
+  int32_t c4_light;
+  int32_t c4_heavy;
+  int32_t max_ucnt;
+  int32_t max_lcnt_heavy;
+  int32_t max_deg;
+  int32_t pad[6];
+  u64 wedges_light;
+  u64 wedges_heavy;
+  u64 clique_entries;
+  u64 pad2;
+};
+
+__device__ __forceinline__ void flag_err(int32_t *err, int code) { atomicOr(err, 1 << (-code)); }
+
+inline unsigned grid1d(int64_t n, int block, int64_t cap = 1 << 20) {
+  int64_t g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+// ---------------------------------------------------------------- prepass
+
+struct PrepassArgs {
+  const int32_t *row_ptr, *col;  // caller's CSR
+  int64_t n, nnz;
+  int B;                          // bits of a vertex id
+  DevAcc *acc;
+  Counters *cnt;
+  // outputs
+  int32_t *deg, *order, *rank, *deg2, *rp2, *col2, *lcnt, *ucnt, *ustart, *tpos;
+  u64 *rkeys, *rkeys_alt, *ekeys, *ekeys_alt, *W;
+  int32_t *tk[kTkBins], *c4l, *c4h;
+  u64 *esorted;  // set by the prepass: sorted (row << B | col) keys
+};
+
+// Maximum degree and maximum |U(x)| of a caller CSR (one sync on s).
+int probe_graph(const gc_csr *g, hipStream_t s, int *max_deg, int *max_ucnt);
+int launch_validate(const int32_t *rp, const int32_t *col, int64_t n, int64_t nnz, int32_t *err,
+                    hipStream_t s);
+int run_prepass(PrepassArgs &p, Arena &a, hipStream_t s);
+// Heavy wedge items (x, y_begin, y_end), largest first, built on the device.
+int build_heavy_items(const PrepassArgs &p, int nheavy, int4 *items, u64 *keys, u64 *keys_alt,
+                      int64_t *pcount, Arena &a, hipStream_t s);
+void measure_heavy_items(int nheavy, Arena &a);
+
+// ---------------------------------------------------------------- cliques
+
+struct TkArgs {
+  const int32_t *col2;
+  const int32_t *ustart;
+  const int32_t *ucnt;
+  const int32_t *list;
+  int nlist;
+  uint32_t *T;  // |Tri| per upper position
+  u64 *K4w;     // per-edge pass: 4-cliques per upper position
+  u64 *Dw;      // per-edge pass: D_e per upper position
+  u64 *k4;      // global mode: number of 4-cliques (128-bit)
+  u64 *k4x3;    // fallback kernel: 3 x 4-cliques (128-bit)
+  // global storage of the fallback kernel, per workgroup slot
+  u64 *gR;
+  int32_t *gI;
+  u64 *gA;
+  int kmax;
+};
+
+// Launches the clique pass for one size class.
+int launch_cliques(TkArgs g, int bin, bool per_edge, hipStream_t s);
+// Whether a class needs the global-memory scratch in the given mode.
+inline bool cliques_need_global(int bin, bool per_edge) { return bin == 4 || (per_edge && bin == 3); }
+
+// ---------------------------------------------------------------- cycles
+
+struct C4Args {
+  const int32_t *col2;
+  const int32_t *rp2;
+  const int32_t *lcnt;
+  const int32_t *tpos;
+  const u64 *W;
+  const int32_t *list;
+  int nlist;
+  u64 *c4ni;  // total (128-bit)
+  u64 *C4w;   // per-edge pass: 4-cycles (chords allowed) per upper position
+  const int4 *items;  // (x, y_begin, y_end, -)
+  const int64_t *nitems;
+  u64 *queue;
+  int32_t *gcur;  // per slot: cursor per lower neighbour
+  int32_t *gbeg;  // per slot (per-edge): cursor at chunk start
+  u64 *gacc;      // per slot (per-edge): credit for edge (x, v)
+  int lmax;
+};
+
+int launch_cycles_light(C4Args g, bool per_edge, hipStream_t s);
+int launch_cycles_heavy(C4Args g, int slots, bool per_edge, hipStream_t s);
+
+// ---------------------------------------------------------------- Step 3
+
+struct S3Args {
+  const u64 *ekeys;
+  const int32_t *col2;
+  const int32_t *deg2;
+  const uint32_t *T;
+  const u64 *K4w, *C4w, *Dw;  // per-edge mode only
+  int64_t nnz, n, m;
+  int B;
+  u64 *partials;  // [grid][kAcc][2]
+  DevAcc *acc;
+  const int32_t *order;
+  const int32_t *rp;
+  const int32_t *col;
+  const int64_t *cu;
+  int64_t *out;  // [3][m]
+};
+
+constexpr int kStep3Grid = 2048;
+int launch_step3(S3Args g, int grid, bool per_edge, hipStream_t s);
+int launch_orig_upper(const int32_t *rp, const int32_t *col, int64_t n, int64_t *up,
+                      hipStream_t s);
+
+}  // namespace gc

@@ -1,0 +1,393 @@
+// Prepass: contract validation, relabelling by degree, re-sorted adjacency,
+// reverse-entry positions, per-vertex work estimates and work lists.
+//
+// The paper's implementation orders neighbour lists and edge jobs by degree
+// (Section 5.2, job batches); here the order is the total order
+// x < y iff (deg x, x) < (deg y, y), applied by relabelling every vertex with
+// its rank.  Under it, every vertex has at most sqrt(2m) upper neighbours,
+// which bounds the per-vertex state of the clique pass, and every 4-cycle has
+// one highest vertex, which the wedge pass aggregates on.
+#include "kernels.h"
+#include "primitives.h"
+
+namespace gc {
+
+namespace {
+
+// Sets bit (-code) of *err for every violation; the host reports the lowest.
+__global__ void k_validate(const int32_t *rp, const int32_t *col, int64_t n, int64_t nnz,
+                           int32_t *err) {
+  int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; u < n; u += stride) {
+    const int64_t a = rp[u], b = rp[u + 1];
+    if (a < 0 || b < a || b > nnz) {
+      flag_err(err, GC_EINVAL);
+      continue;
+    }
+    for (int64_t j = a; j < b; j++) {
+      const int64_t v = col[j];
+      if (v < 0 || v >= n) {
+        flag_err(err, GC_EASYMMETRIC);
+        break;
+      }
+      if (v == u) flag_err(err, GC_ESELFLOOP);
+      if (j > a && col[j - 1] >= v) flag_err(err, GC_ENOTSORTED);
+      const int64_t c = rp[v], d = rp[v + 1];
+      if (c < 0 || d < c || d > nnz) continue;
+      const int pos = lower_bound_dev<int32_t>(col + c, (int)(d - c), (int32_t)u);
+      if (pos >= d - c || col[c + pos] != u) flag_err(err, GC_EASYMMETRIC);
+    }
+  }
+}
+
+__global__ void k_check_rowptr_ends(const int32_t *rp, int64_t n, int64_t nnz, int32_t *err) {
+  if (threadIdx.x == 0 && blockIdx.x == 0)
+    if (rp[0] != 0 || rp[n] != nnz) flag_err(err, GC_EINVAL);
+}
+
+// deg[u] and the key (deg << B | u) ordering vertices by (degree, id).
+__global__ void k_degree_keys(const int32_t *rp, int64_t n, int B, int32_t *deg, u64 *key,
+                              int32_t *max_deg) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int mx = 0;
+  if (u < n) {
+    const int d = rp[u + 1] - rp[u];
+    deg[u] = d;
+    key[u] = ((u64)d << B) | (u64)u;
+    mx = d;
+  }
+  for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, kWave));
+  if (lane_id() == 0 && mx) atomicMax(max_deg, mx);
+}
+
+// order[x] = caller's id of new vertex x; rank[old] = x; deg2[x] = degree.
+__global__ void k_rank(const u64 *sorted, int64_t n, int B, int32_t *order, int32_t *rank,
+                       int32_t *deg2) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  const u64 k = sorted[x];
+  const int32_t old = (int32_t)(k & ((1ull << B) - 1));
+  order[x] = old;
+  rank[old] = (int32_t)x;
+  deg2[x] = (int32_t)(k >> B);
+}
+
+// One wave per row: key (rank[u] << B | rank[w]) for every entry.  An id
+// outside [0, n) (broken contract, no validation) is flagged, never indexed.
+__global__ void k_edge_keys(const int32_t *rp, const int32_t *col, int64_t n, int B,
+                            const int32_t *rank, u64 *ekeys, int32_t *err) {
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  const int lane = lane_id();
+  for (int64_t u = wave; u < n; u += nwaves) {
+    const u64 ru = (u64)rank[u] << B;
+    for (int64_t j = rp[u] + lane; j < rp[u + 1]; j += kWave) {
+      int32_t w = col[j];
+      if (w < 0 || w >= n) {
+        flag_err(err, GC_EASYMMETRIC);
+        w = (int32_t)u;
+      }
+      ekeys[j] = ru | (u64)rank[w];
+    }
+  }
+}
+
+__global__ void k_split_keys(const u64 *ekeys, int64_t nnz, int B, int32_t *col2) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < nnz) col2[p] = (int32_t)(ekeys[p] & ((1ull << B) - 1));
+}
+
+// lcnt[x] = |L(x)|, ucnt[x] = |U(x)|, ustart[x] = first upper position.
+__global__ void k_split_rows(const int32_t *rp2, const int32_t *col2, int64_t n, int32_t *lcnt,
+                             int32_t *ucnt, int32_t *ustart, int32_t *max_ucnt) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int mx = 0;
+  if (x < n) {
+    const int a = rp2[x], d = rp2[x + 1] - a;
+    const int l = lower_bound_dev<int32_t>(col2 + a, d, (int32_t)x);
+    lcnt[x] = l;
+    ucnt[x] = d - l;
+    ustart[x] = a + l;
+    mx = d - l;
+  }
+  for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, kWave));
+  if (lane_id() == 0 && mx) atomicMax(max_ucnt, mx);
+}
+
+// tpos[p] = position of the reverse entry (x in the list of y).  Every
+// position is written; a missing reverse entry or a self-loop is flagged and
+// points at p itself.
+__global__ void k_tpos(const u64 *ekeys, const int32_t *col2, const int32_t *rp2,
+                       const int32_t *lcnt, int64_t nnz, int B, int32_t *tpos, int32_t *err) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nnz) return;
+  const int32_t x = (int32_t)(ekeys[p] >> B);
+  const int32_t y = col2[p];
+  int a, len;
+  if (y > x) {
+    a = rp2[y];
+    len = lcnt[y];
+  } else {
+    a = rp2[y] + lcnt[y];
+    len = rp2[y + 1] - a;
+  }
+  const int q = a + lower_bound_dev<int32_t>(col2 + a, len, x);
+  if (y == x || q >= a + len || col2[q] != x) {
+    flag_err(err, y == x ? GC_ESELFLOOP : GC_EASYMMETRIC);
+    tpos[p] = (int32_t)p;
+    return;
+  }
+  tpos[p] = q;
+}
+
+// W[x] = wedges x - v - y with v, y below x: sum over v in L(x) of the length
+// of the prefix of N(v) below x, which ends at tpos[q] (x's own position in
+// N(v)).  Also counts the entries the clique pass scans: vertex v reads U(x)
+// for every x in U(v), i.e. |U(x)| per lower position (x, v).
+__global__ __launch_bounds__(256) void k_wedges(const u64 *ekeys, const int32_t *col2,
+                                                const int32_t *rp2, const int32_t *tpos,
+                                                const int32_t *ucnt, int64_t nnz, int B, u64 *W,
+                                                u64 *clique_entries) {
+  __shared__ u64 red[4];
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int32_t x = -1;
+  u64 len = 0, ce = 0;
+  if (p < nnz) {
+    const int32_t r = (int32_t)(ekeys[p] >> B);
+    const int32_t v = col2[p];
+    if (v < r) {
+      x = r;
+      len = (u64)(tpos[p] - rp2[v]);
+      ce = (u64)ucnt[r];
+    }
+  }
+  // one atomic per (wave, row) run for W; one per block for the entry count
+  const int32_t x0 = __shfl(x, 0, kWave);
+  if (__all(x == x0)) {
+    const u64 s = wave_sum_u64(len);
+    if (lane_id() == 0 && x0 >= 0 && s) atomicAdd(&W[x0], s);
+  } else if (x >= 0 && len) {
+    atomicAdd(&W[x], len);
+  }
+  ce = wave_sum_u64(ce);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = ce;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const u64 t = red[0] + red[1] + red[2] + red[3];
+    if (t) atomicAdd(clique_entries, t);
+  }
+}
+
+// Wave-aggregated append of x to list L (counter *cnt): one atomic per wave.
+__device__ __forceinline__ void wave_append(bool cond, int32_t x, int32_t *list, int32_t *cnt) {
+  const u64 mask = __ballot(cond);
+  if (!mask) return;
+  const int leader = __ffsll((long long)mask) - 1;
+  int base = 0;
+  if (lane_id() == leader) base = atomicAdd(cnt, __popcll(mask));
+  base = __shfl(base, leader, kWave);
+  if (cond) list[base + __popcll(mask & lanemask_lt())] = x;
+}
+
+// Work lists: clique classes by |U(u)| (>= 2), wedge vertices light/heavy.
+__global__ __launch_bounds__(256) void k_bins(const int32_t *ucnt, const int32_t *lcnt,
+                                              const u64 *W, int64_t n, int32_t *tk0, int32_t *tk1,
+                                              int32_t *tk2, int32_t *tk3, int32_t *tk4,
+                                              int32_t *c4l, int32_t *c4h, Counters *cnt) {
+  __shared__ u64 red[2][4];
+  const int64_t xi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = xi < n;
+  const int32_t x = (int32_t)xi;
+  const int k = in ? ucnt[x] : 0;
+  const u64 w = in ? W[x] : 0;
+  const int cls = k >= 2 ? tk_class(k) : -1;
+  wave_append(cls == 0, x, tk0, &cnt->tk_cnt[0]);
+  wave_append(cls == 1, x, tk1, &cnt->tk_cnt[1]);
+  wave_append(cls == 2, x, tk2, &cnt->tk_cnt[2]);
+  wave_append(cls == 3, x, tk3, &cnt->tk_cnt[3]);
+  wave_append(cls == 4, x, tk4, &cnt->tk_cnt[4]);
+  const bool light = w >= 2 && w <= kLightWedges;  // one wedge cannot close a cycle
+  const bool heavy = w > kLightWedges;
+  wave_append(light, x, c4l, &cnt->c4_light);
+  wave_append(heavy, x, c4h, &cnt->c4_heavy);
+  int ml = heavy ? lcnt[x] : 0;
+  for (int off = 32; off > 0; off >>= 1) ml = max(ml, __shfl_xor(ml, off, kWave));
+  if (lane_id() == 0 && ml) atomicMax(&cnt->max_lcnt_heavy, ml);
+  const u64 wl = wave_sum_u64(light ? w : 0), wh = wave_sum_u64(heavy ? w : 0);
+  if (lane_id() == 0) {
+    red[0][threadIdx.x / kWave] = wl;
+    red[1][threadIdx.x / kWave] = wh;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const u64 a = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    const u64 b = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    if (a) atomicAdd(&cnt->wedges_light, a);
+    if (b) atomicAdd(&cnt->wedges_heavy, b);
+  }
+}
+
+// ------------------------------------------------------------ heavy items
+
+// Sort key: larger work first (32-bit clamped), then list index.
+__global__ void k_heavy_keys(const int32_t *c4h, int nh, const u64 *W, u64 *keys) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nh) return;
+  const u64 w = W[c4h[i]];
+  const u64 wc = w > 0xffffffffull ? 0xffffffffull : w;
+  keys[i] = ((0xffffffffull - wc) << 32) | (u64)i;
+}
+
+__device__ __forceinline__ int chunk_span(int nl) { return nl < 65536 ? 2 * kChunkWords : kChunkWords; }
+
+// Pieces of a heavy vertex: y range [0, x) cut into about W / kPieceWork
+// pieces, at most one per LDS chunk.
+__global__ void k_heavy_pieces(const u64 *sorted, int nh, const int32_t *c4h, const u64 *W,
+                               const int32_t *lcnt, int64_t *pcount) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nh) return;
+  const int x = c4h[(int)(sorted[s] & 0xffffffffull)];
+  const int64_t K = chunk_span(lcnt[x]);
+  const int64_t nchunks = ((int64_t)x + K - 1) / K;
+  int64_t S = (int64_t)((W[x] + kPieceWork - 1) / kPieceWork);
+  if (S > nchunks) S = nchunks;
+  if (S < 1) S = 1;
+  pcount[s] = S;
+}
+
+__global__ void k_heavy_expand(const u64 *sorted, int nh, const int32_t *c4h,
+                               const int32_t *lcnt, const int64_t *poff, const int64_t *pcount,
+                               int4 *items, int64_t *nitems) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nh) return;
+  const int x = c4h[(int)(sorted[s] & 0xffffffffull)];
+  const int64_t K = chunk_span(lcnt[x]);
+  const int64_t nchunks = ((int64_t)x + K - 1) / K;
+  const int64_t S = pcount[s], base = poff[s];
+  for (int64_t k = 0; k < S; k++) {
+    const int64_t c0 = nchunks * k / S, c1 = nchunks * (k + 1) / S;
+    const int ya = (int)(c0 * K);
+    const int yb = (int)(c1 * K < x ? c1 * K : x);
+    items[base + k] = make_int4(x, ya, yb, 0);
+  }
+  if (s == nh - 1) *nitems = base + S;
+}
+
+__global__ void k_max_deg(const int32_t *rp, int64_t n, int32_t *out) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int mx = 0;
+  if (u < n) mx = rp[u + 1] - rp[u];
+  for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, kWave));
+  if (lane_id() == 0 && mx) atomicMax(out, mx);
+}
+
+// max over vertices of |U(x)|: neighbours later in the (degree, id) order.
+__global__ void k_max_ucnt(const int32_t *rp, const int32_t *col, int64_t n, int32_t *out) {
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  const int lane = lane_id();
+  for (int64_t u = wave; u < n; u += nwaves) {
+    const int a = rp[u], b = rp[u + 1], du = b - a;
+    int c = 0;
+    for (int j = a + lane; j < b; j += kWave) {
+      const int w = col[j];
+      if (w < 0 || w >= n) continue;  // broken contract: never used as an index
+      const int dw = rp[w + 1] - rp[w];
+      c += (dw > du || (dw == du && w > u)) ? 1 : 0;
+    }
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, kWave);
+    if (lane == 0 && c) atomicMax(out, c);
+  }
+}
+
+}  // namespace
+
+int probe_graph(const gc_csr *g, hipStream_t s, int *max_deg, int *max_ucnt) {
+  *max_deg = 0;
+  *max_ucnt = 0;
+  if (g->n == 0 || g->nnz == 0) return GC_OK;
+  int32_t *d = nullptr;
+  GC_TRY_HIP(hipMallocAsync((void **)&d, 8, s));
+  int32_t h[2] = {0, 0};
+  hipError_t e = hipMemcpyAsync(d, h, 8, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    k_max_deg<<<grid1d(g->n, 256), 256, 0, s>>>(g->row_ptr, g->n, d);
+    k_max_ucnt<<<grid1d(g->n * kWave, 256, 65536), 256, 0, s>>>(g->row_ptr, g->col, g->n, d + 1);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(h, d, 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  const hipError_t f = hipFreeAsync(d, s);
+  if (e == hipSuccess) e = f;
+  if (e != hipSuccess) {
+    set_error("probe: %s", hipGetErrorString(e));
+    return GC_EHIP;
+  }
+  *max_deg = h[0];
+  *max_ucnt = h[1];
+  return GC_OK;
+}
+
+int launch_validate(const int32_t *rp, const int32_t *col, int64_t n, int64_t nnz, int32_t *err,
+                    hipStream_t s) {
+  k_check_rowptr_ends<<<1, 64, 0, s>>>(rp, n, nnz, err);
+  k_validate<<<grid1d(n, 256, 16384), 256, 0, s>>>(rp, col, n, nnz, err);
+  GC_TRY_HIP(hipGetLastError());
+  return GC_OK;
+}
+
+int run_prepass(PrepassArgs &p, Arena &a, hipStream_t s) {
+  const int64_t n = p.n, nnz = p.nnz;
+  const int B = p.B;
+  k_degree_keys<<<grid1d(n, 256), 256, 0, s>>>(p.row_ptr, n, B, p.deg, p.rkeys, &p.cnt->max_deg);
+  GC_TRY_HIP(hipGetLastError());
+  u64 *rsorted;
+  GC_TRY(radix_sort_u64(p.rkeys, p.rkeys_alt, n, B + bits_for((u64)nnz), &rsorted, a, s));
+  k_rank<<<grid1d(n, 256), 256, 0, s>>>(rsorted, n, B, p.order, p.rank, p.deg2);
+  GC_TRY_HIP(hipGetLastError());
+  GC_TRY(scan_exclusive<int32_t>(p.deg2, p.rp2, n, a, s));
+  GC_TRY(fill<int32_t>(p.rp2 + n, (int32_t)nnz, 1, s));
+  k_edge_keys<<<grid1d(n * kWave, 256, 65536), 256, 0, s>>>(p.row_ptr, p.col, n, B, p.rank,
+                                                           p.ekeys, &p.acc->err);
+  GC_TRY_HIP(hipGetLastError());
+  GC_TRY(radix_sort_u64(p.ekeys, p.ekeys_alt, nnz, 2 * B, &p.esorted, a, s));
+  k_split_keys<<<grid1d(nnz, 256), 256, 0, s>>>(p.esorted, nnz, B, p.col2);
+  k_split_rows<<<grid1d(n, 256), 256, 0, s>>>(p.rp2, p.col2, n, p.lcnt, p.ucnt, p.ustart,
+                                              &p.cnt->max_ucnt);
+  k_tpos<<<grid1d(nnz, 256), 256, 0, s>>>(p.esorted, p.col2, p.rp2, p.lcnt, nnz, B, p.tpos,
+                                          &p.acc->err);
+  k_wedges<<<grid1d(nnz, 256), 256, 0, s>>>(p.esorted, p.col2, p.rp2, p.tpos, p.ucnt, nnz, B, p.W,
+                                            &p.cnt->clique_entries);
+  k_bins<<<grid1d(n, 256), 256, 0, s>>>(p.ucnt, p.lcnt, p.W, n, p.tk[0], p.tk[1], p.tk[2],
+                                        p.tk[3], p.tk[4], p.c4l, p.c4h, p.cnt);
+  GC_TRY_HIP(hipGetLastError());
+  return GC_OK;
+}
+
+void measure_heavy_items(int nheavy, Arena &a) {
+  size_t m0 = a.mark();
+  u64 *dummy;
+  (void)radix_sort_u64(nullptr, nullptr, nheavy, 64, &dummy, a, nullptr);
+  (void)scan_exclusive<int64_t>(nullptr, nullptr, nheavy, a, nullptr);
+  a.release(m0);
+}
+
+int build_heavy_items(const PrepassArgs &p, int nh, int4 *items, u64 *keys, u64 *keys_alt,
+                      int64_t *pcount, Arena &a, hipStream_t s) {
+  if (nh <= 0) return GC_OK;
+  k_heavy_keys<<<grid1d(nh, 256), 256, 0, s>>>(p.c4h, nh, p.W, keys);
+  GC_TRY_HIP(hipGetLastError());
+  u64 *sorted;
+  GC_TRY(radix_sort_u64(keys, keys_alt, nh, 32 + bits_for((u64)nh), &sorted, a, s));
+  k_heavy_pieces<<<grid1d(nh, 256), 256, 0, s>>>(sorted, nh, p.c4h, p.W, p.lcnt, pcount);
+  GC_TRY_HIP(hipGetLastError());
+  int64_t *poff = reinterpret_cast<int64_t *>(sorted == keys ? keys_alt : keys);
+  GC_TRY(scan_exclusive<int64_t>(pcount, poff, nh, a, s));
+  k_heavy_expand<<<grid1d(nh, 256), 256, 0, s>>>(sorted, nh, p.c4h, p.lcnt, poff, pcount, items,
+                                                 &p.acc->nitems);
+  GC_TRY_HIP(hipGetLastError());
+  return GC_OK;
+}
+
+}  // namespace gc

@@ -1,0 +1,114 @@
+// Step 3: per edge, the unrestricted counts of Section 4.2 in constant time,
+// summed exactly.
+//
+// For e = (u, v) with T = |Tri_e|, Su = |Star_u| = d_u - 1 - T,
+// Sv = |Star_v| = d_v - 1 - T and I = |V| - |N(u) u N(v)| = n - d_u - d_v + T
+// (the union holds u and v themselves), Equations "comb_n_ai_ai" and
+// "comb_n_ai_aj" give N_{T,T} = C(T,2), N_{Su,Sv} = Su Sv, ..., N_{I,I} =
+// C(I,2), and the graphlet counting algorithm adds |E| - d_u - d_v + 1 toward
+// N_{I,I,1}.  Every per-edge term fits 64 bits (each factor is below 2^31);
+// the sums do not (C(I,2) summed over R-MAT scale 22 is ~5e20), so each
+// thread accumulates in 128 bits and blocks reduce exactly.
+#include "kernels.h"
+
+namespace gc {
+
+namespace {
+
+__device__ __forceinline__ u64 choose2(u64 c) { return c * (c - 1) / 2; }
+
+template <bool PER_EDGE>
+__global__ __launch_bounds__(256) void k_step3(S3Args g) {
+  __shared__ u64 red[32];
+  u128 a[kAcc];
+#pragma unroll
+  for (int i = 0; i < kAcc; i++) a[i] = 0;
+  const u64 n = (u64)g.n, m = (u64)g.m;
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; p < g.nnz; p += stride) {
+    const int32_t x = (int32_t)(g.ekeys[p] >> g.B);
+    const int32_t y = g.col2[p];
+    if (y <= x) continue;  // each undirected edge once, at its upper position
+    const u64 du = (u64)g.deg2[x], dv = (u64)g.deg2[y];
+    const u64 T = g.T[p];
+    const u64 Su = du - 1 - T, Sv = dv - 1 - T, S = Su + Sv;
+    const u64 I = n - du - dv + T;
+    a[A_T] += T;
+    a[A_S] += S;
+    a[A_I] += I;
+    a[A_TT] += choose2(T);
+    a[A_SUSV] += (u128)Su * Sv;
+    a[A_TS] += (u128)T * S;
+    a[A_SS] += (u128)choose2(Su) + choose2(Sv);
+    a[A_TI] += (u128)T * I;
+    a[A_SI] += (u128)S * I;
+    a[A_II] += I ? (u128)choose2(I) : (u128)0;
+    a[A_II1] += m - du - dv + 1;
+    if (PER_EDGE) {
+      const u64 k4 = g.K4w[p];
+      const u64 c4 = g.C4w[p] - g.Dw[p] + 2 * k4;  // non-negative; wraps cancel
+      a[A_K4] += k4;
+      a[A_C4] += c4;
+      // canonical id of the edge in the caller's numbering
+      const int32_t ua = g.order[x], ub = g.order[y];
+      const int32_t lo = ua < ub ? ua : ub, hi = ua < ub ? ub : ua;
+      const int32_t r0 = g.rp[lo], r1 = g.rp[lo + 1];
+      const int split = lower_bound_dev<int32_t>(g.col + r0, r1 - r0, lo);
+      const int pos = lower_bound_dev<int32_t>(g.col + r0, r1 - r0, hi);
+      const int64_t id = g.cu[lo] + (pos - split);
+      g.out[id] = (int64_t)T;
+      g.out[g.m + id] = (int64_t)k4;
+      g.out[2 * g.m + id] = (int64_t)c4;
+    }
+  }
+  for (int i = 0; i < kAcc; i++) {
+    const u128 s = block_sum_u128(a[i], red);
+    if (threadIdx.x == 0) {
+      g.partials[((size_t)blockIdx.x * kAcc + i) * 2] = (u64)s;
+      g.partials[((size_t)blockIdx.x * kAcc + i) * 2 + 1] = (u64)(s >> 64);
+    }
+  }
+}
+
+// One wave per accumulator sums the block partials.
+__global__ void k_step3_final(const u64 *partials, int nblocks, DevAcc *acc) {
+  const int i = blockIdx.x;
+  u128 s = 0;
+  for (int b = threadIdx.x; b < nblocks; b += kWave)
+    s += ((u128)partials[((size_t)b * kAcc + i) * 2 + 1] << 64) |
+         partials[((size_t)b * kAcc + i) * 2];
+  s = wave_sum_u128(s);
+  if (threadIdx.x == 0) {
+    acc->step3[i][0] = (u64)s;
+    acc->step3[i][1] = (u64)(s >> 64);
+  }
+}
+
+// Upper-neighbour counts in the caller's ids (canonical edge numbering).
+__global__ void k_orig_upper(const int32_t *rp, const int32_t *col, int64_t n, int64_t *up) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  const int a = rp[u], d = rp[u + 1] - a;
+  up[u] = d - lower_bound_dev<int32_t>(col + a, d, (int32_t)u);
+}
+
+}  // namespace
+
+int launch_step3(S3Args g, int grid, bool per_edge, hipStream_t s) {
+  if (per_edge) k_step3<true><<<grid, 256, 0, s>>>(g);
+  else k_step3<false><<<grid, 256, 0, s>>>(g);
+  GC_TRY_HIP(hipGetLastError());
+  k_step3_final<<<kAcc, kWave, 0, s>>>(g.partials, grid, g.acc);
+  GC_TRY_HIP(hipGetLastError());
+  return GC_OK;
+}
+
+int launch_orig_upper(const int32_t *rp, const int32_t *col, int64_t n, int64_t *up,
+                      hipStream_t s) {
+  k_orig_upper<<<grid1d(n, 256), 256, 0, s>>>(rp, col, n, up);
+  GC_TRY_HIP(hipGetLastError());
+  return GC_OK;
+}
+
+}  // namespace gc
