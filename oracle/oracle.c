@@ -402,50 +402,65 @@ int oracle_identity_route(int64_t n, const int32_t *rp, const int32_t *col, orc_
           eid[j] = eid[lo];
         }
   }
-  /* Triangles: each found once from its lowest vertex x (in the order), as
-   * x < y < z with y, z in N(x) and z in N(y).  mark[z] = slot of (x,z)+1. */
+  /* Upper lists: up[x] = neighbours later than x in the order, each with the
+   * undirected id of its edge; every triangle and clique below is listed once
+   * from its lowest vertex, reading upper lists only. */
+  int64_t *up_ptr = (int64_t *)calloc((size_t)(n + 1), sizeof(int64_t));
+  int64_t *up_col = (int64_t *)malloc(sizeof(int64_t) * (m2 / 2 + 1));
+  int64_t *up_eid = (int64_t *)malloc(sizeof(int64_t) * (m2 / 2 + 1));
+  if (!up_ptr || !up_col || !up_eid) {
+    free(up_ptr); free(up_col); free(up_eid);
+    free(deg); free(pos); free(eid); free(te); free(tv); free(mark); free(mark2); free(cnt);
+    free(touched); free(ord);
+    return -3;
+  }
+  for (int64_t x = 0; x < n; x++) {
+    up_ptr[x + 1] = up_ptr[x];
+    for (int64_t j = rp[x]; j < rp[x + 1]; j++)
+      if (pos[col[j]] > pos[x]) {
+        up_col[up_ptr[x + 1]] = col[j];
+        up_eid[up_ptr[x + 1]] = eid[j];
+        up_ptr[x + 1]++;
+      }
+  }
+  /* Triangles x < y < z: y in up(x), z in up(y) and in up(x).
+   * mark[z] = 1 + undirected id of (x, z). */
   u128 t = 0, k4 = 0;
   for (int64_t v = 0; v < n; v++) { mark[v] = 0; mark2[v] = 0; }
   for (int64_t x = 0; x < n; x++) {
-    for (int64_t j = rp[x]; j < rp[x + 1]; j++)
-      if (pos[col[j]] > pos[x]) mark[col[j]] = j + 1;
-    for (int64_t j = rp[x]; j < rp[x + 1]; j++) {
-      int64_t y = col[j];
-      if (pos[y] <= pos[x]) continue;
-      for (int64_t q = rp[y]; q < rp[y + 1]; q++) {
-        int64_t z = col[q];
-        if (pos[z] <= pos[y] || !mark[z]) continue;
+    for (int64_t j = up_ptr[x]; j < up_ptr[x + 1]; j++) mark[up_col[j]] = up_eid[j] + 1;
+    for (int64_t j = up_ptr[x]; j < up_ptr[x + 1]; j++) {
+      int64_t y = up_col[j];
+      for (int64_t q = up_ptr[y]; q < up_ptr[y + 1]; q++) {
+        int64_t z = up_col[q];
+        if (!mark[z]) continue;
         t++;
-        te[eid[j]]++;
-        te[eid[q]]++;
-        te[eid[mark[z] - 1]]++;
+        te[up_eid[j]]++;
+        te[up_eid[q]]++;
+        te[mark[z] - 1]++;
         tv[x]++; tv[y]++; tv[z]++;
       }
     }
-    for (int64_t j = rp[x]; j < rp[x + 1]; j++) mark[col[j]] = 0;
+    for (int64_t j = up_ptr[x]; j < up_ptr[x + 1]; j++) mark[up_col[j]] = 0;
   }
-  /* 4-cliques: each found once from its lowest vertex x as x < y < z < w,
-   * all of y, z, w in N(x), z, w in N(y), w in N(z). */
+  /* 4-cliques x < y < z < w: y in up(x); z, w in up(x) and up(y); w in up(z). */
   for (int64_t x = 0; x < n; x++) {
-    for (int64_t j = rp[x]; j < rp[x + 1]; j++)
-      if (pos[col[j]] > pos[x]) mark[col[j]] = 1;
-    for (int64_t j = rp[x]; j < rp[x + 1]; j++) {
-      int64_t y = col[j];
-      if (pos[y] <= pos[x]) continue;
-      for (int64_t q = rp[y]; q < rp[y + 1]; q++)
-        if (pos[col[q]] > pos[y] && mark[col[q]]) mark2[col[q]] = 1; /* z, w candidates */
-      for (int64_t q = rp[y]; q < rp[y + 1]; q++) {
-        int64_t z = col[q];
-        if (pos[z] <= pos[y] || !mark2[z]) continue;
-        for (int64_t r = rp[z]; r < rp[z + 1]; r++) {
-          int64_t w = col[r];
-          if (pos[w] > pos[z] && mark2[w]) k4++;
-        }
+    for (int64_t j = up_ptr[x]; j < up_ptr[x + 1]; j++) mark[up_col[j]] = 1;
+    for (int64_t j = up_ptr[x]; j < up_ptr[x + 1]; j++) {
+      int64_t y = up_col[j];
+      for (int64_t q = up_ptr[y]; q < up_ptr[y + 1]; q++)
+        if (mark[up_col[q]]) mark2[up_col[q]] = 1;
+      for (int64_t q = up_ptr[y]; q < up_ptr[y + 1]; q++) {
+        int64_t z = up_col[q];
+        if (!mark2[z]) continue;
+        for (int64_t r = up_ptr[z]; r < up_ptr[z + 1]; r++)
+          if (mark2[up_col[r]]) k4++;
       }
-      for (int64_t q = rp[y]; q < rp[y + 1]; q++) mark2[col[q]] = 0;
+      for (int64_t q = up_ptr[y]; q < up_ptr[y + 1]; q++) mark2[up_col[q]] = 0;
     }
-    for (int64_t j = rp[x]; j < rp[x + 1]; j++) mark[col[j]] = 0;
+    for (int64_t j = up_ptr[x]; j < up_ptr[x + 1]; j++) mark[up_col[j]] = 0;
   }
+  free(up_ptr); free(up_col); free(up_eid);
   /* 4-cycles (non-induced): each cycle has one highest vertex x; with y the
    * vertex opposite x, the cycle is two paths x - v - y with v, y below x.
    * cnt[y] counts such paths; the cycles with that (x, y) are C(cnt[y], 2). */
