@@ -8,7 +8,7 @@
 #include <cstdio>
 #include <string>
 
-#include "../../include/graphlet.h"
+#include "graphlet.h"
 
 namespace gc {
 

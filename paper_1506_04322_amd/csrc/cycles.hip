@@ -219,7 +219,280 @@ __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy(C4Args g) {
   if (threadIdx.x == 0 && s) atomic_add_u128(g.c4ni, s);
 }
 
+// Exclusive scan of A[0..k) in place, total in A[k]; BLOCK threads, three
+// barriers (wave scans by shuffles, one wave scans the wave totals).
+template <int BLOCK>
+__device__ void scan_excl(int32_t *A, int k, int32_t *wsum) {
+  constexpr int NW = BLOCK / kWave;
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+  const int per = (k + BLOCK - 1) / BLOCK;
+  const int a = min(k, tid * per), b = min(k, a + per);
+  int32_t s = 0;
+  for (int i = a; i < b; i++) s += A[i];
+  int32_t incl = s;
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int32_t t = __shfl_up(incl, off, kWave);
+    if (lane >= off) incl += t;
+  }
+  if (lane == kWave - 1) wsum[wave] = incl;
+  __syncthreads();
+  if (wave == 0) {
+    int32_t v = lane < NW ? wsum[lane] : 0;
+    int32_t vi = v;
+    for (int off = 1; off < kWave; off <<= 1) {
+      const int32_t t = __shfl_up(vi, off, kWave);
+      if (lane >= off) vi += t;
+    }
+    if (lane < NW) wsum[lane] = vi - v;
+    if (lane == NW - 1) wsum[NW] = vi;
+  }
+  __syncthreads();
+  int32_t run = wsum[wave] + incl - s;
+  for (int i = a; i < b; i++) {
+    const int32_t v = A[i];
+    A[i] = run;
+    run += v;
+  }
+  if (tid == 0) A[k] = wsum[NW];
+  __syncthreads();
+}
+
+// Medium x (global mode): one workgroup per vertex, c(x, .) in an LDS hash
+// of up to kMediumSlots slots; wedges enumerated flat over batches of lower
+// neighbours so every thread reads a share of each batch.
+__global__ __launch_bounds__(kMediumBlock) void k_c4_medium(C4Args g) {
+  __shared__ int32_t hkey[kMediumSlots];
+  __shared__ uint32_t hcnt[kMediumSlots];
+  __shared__ int32_t sPre[kMediumBlock + 1], sStart[kMediumBlock], sums[kMediumBlock / kWave + 1];
+  __shared__ u64 red[32];
+  const int tid = threadIdx.x;
+  for (int h = tid; h < kMediumSlots; h += kMediumBlock) {
+    hkey[h] = -1;
+    hcnt[h] = 0;
+  }
+  __syncthreads();
+  u128 acc = 0;
+  for (int it = blockIdx.x; it < g.nlist; it += gridDim.x) {
+    const int x = g.list[it];
+    const u64 w = g.W[x];
+    int hs = 64;
+    while ((u64)hs < 2 * w) hs <<= 1;
+    const uint32_t mask = (uint32_t)hs - 1;
+    const int hbits = __ffs(hs) - 1;
+    const int Lx = g.rp2[x], nL = g.lcnt[x];
+    for (int b = 0; b < nL; b += kMediumBlock) {
+      const int nb = min(kMediumBlock, nL - b);
+      if (tid < nb) {
+        const int q = Lx + b + tid;
+        const int s = g.rp2[g.col2[q]];
+        sStart[tid] = s;
+        sPre[tid] = g.tpos[q] - s;
+      }
+      __syncthreads();
+      scan_excl<kMediumBlock>(sPre, nb, sums);
+      const int total = sPre[nb];
+      for (int t = tid; t < total; t += kMediumBlock) {
+        const int o = upper_index_dev<int32_t>(sPre, nb, t);
+        const int y = g.col2[sStart[o] + (t - sPre[o])];
+        uint32_t h = ((uint32_t)y * 2654435761u) >> (32 - hbits);
+        while (true) {
+          const int old = atomicCAS(&hkey[h], -1, y);
+          if (old == -1 || old == y) {
+            atomicAdd(&hcnt[h], 1u);
+            break;
+          }
+          h = (h + 1) & mask;
+        }
+      }
+      __syncthreads();
+    }
+    u64 part = 0;
+    for (int h = tid; h < hs; h += kMediumBlock) {
+      if (hkey[h] != -1) {
+        part += choose2(hcnt[h]);
+        hkey[h] = -1;
+        hcnt[h] = 0;
+      }
+    }
+    acc += (u128)part;
+    __syncthreads();
+  }
+  const u128 s = block_sum_u128(acc, red);
+  if (threadIdx.x == 0 && s) atomic_add_u128(g.c4ni, s);
+}
+
+// Number of entries of the sorted run [p, e) below c1 (exponential then
+// binary search: about 2 log2(result) reads).
+__device__ __forceinline__ int count_below(const int32_t *col2, int p, int e, int c1) {
+  if (p >= e || col2[p] >= c1) return 0;
+  int lo = p, hi = p + 1, step = 1;  // col2[lo] < c1
+  while (hi < e && col2[hi] < c1) {
+    lo = hi;
+    step <<= 1;
+    hi = p + step;
+  }
+  if (hi > e) hi = e;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (col2[mid] < c1) lo = mid;
+    else hi = mid;
+  }
+  return hi - p;
+}
+
+// Heavy x, global mode, balanced.  Per item: the lower neighbours with at
+// least one wedge in the item's y range are compacted (cursor, end, next
+// entry).  Per chunk: the lists whose next entry falls in the chunk are
+// selected by a coalesced pass over the next entries; in groups, the run of
+// each selected list inside the chunk is measured, then the runs are read
+// flat, so threads share long and short lists evenly and neighbouring
+// threads read neighbouring entries.  Counters are zero between chunks: a
+// chunk with few wedges is summed and cleared by revisiting its wedges (the
+// first visitor of a counter takes its value), a dense one by a sweep.
+__global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
+  __shared__ uint32_t cnt[kChunkWords];
+  __shared__ int32_t vpre[kHeavyGroup + 1], vcur[kHeavyGroup], sums[kC4HeavyBlock / kWave + 1];
+  __shared__ u64 red[32];
+  __shared__ int s_item, s_nact, s_nsel;
+  constexpr int RUN = 4;
+  const int tid = threadIdx.x;
+  const int64_t nitems = *g.nitems;
+  int32_t *cur = g.gcur + (size_t)blockIdx.x * g.lmax;
+  int32_t *end = g.gbeg + (size_t)blockIdx.x * g.lmax;
+  int32_t *nxt = g.gnext + (size_t)blockIdx.x * g.lmax;
+  int32_t *sel = g.gsel + (size_t)blockIdx.x * g.lmax;
+  for (int w = tid; w < kChunkWords; w += kC4HeavyBlock) cnt[w] = 0;
+  u128 acc = 0;
+  while (true) {
+    if (tid == 0) {
+      s_item = (int)atomicAdd(g.queue, 1ull);
+      s_nact = 0;
+    }
+    __syncthreads();
+    const int item = s_item;
+    if (item >= nitems) break;
+    const int4 it = g.items[item];
+    const int x = it.x, ya = it.y, yb = it.z;
+    const int Lx = g.rp2[x], nL = g.lcnt[x];
+    const bool packed = nL < 65536;
+    const int K = packed ? 2 * kChunkWords : kChunkWords;
+    // compact the lists with entries in [ya, yb)
+    for (int b0 = 0; b0 < nL; b0 += kC4HeavyBlock) {
+      const int i = b0 + tid;
+      int c = 0, e = 0, y = 0;
+      bool act = false;
+      if (i < nL) {
+        const int q = Lx + i;
+        const int s = g.rp2[g.col2[q]];
+        e = g.tpos[q];
+        c = s + lower_bound_dev<int32_t>(g.col2 + s, e - s, ya);
+        if (c < e) {
+          y = g.col2[c];
+          act = y < yb;
+        }
+      }
+      const u64 mask = __ballot(act);
+      int base = 0;
+      if (lane_id() == 0 && mask) base = atomicAdd(&s_nact, __popcll(mask));
+      base = __shfl(base, 0, kWave);
+      if (act) {
+        const int o = base + __popcll(mask & lanemask_lt());
+        cur[o] = c;
+        end[o] = e;
+        nxt[o] = y;
+      }
+    }
+    __syncthreads();
+    const int nA = s_nact;
+    for (int c0 = ya; c0 < yb; c0 += K) {
+      const int c1 = min(c0 + K, yb);
+      if (tid == 0) s_nsel = 0;
+      __syncthreads();
+      for (int b0 = 0; b0 < nA; b0 += kC4HeavyBlock) {
+        const int i = b0 + tid;
+        const bool in = i < nA && nxt[i] < c1;
+        const u64 mask = __ballot(in);
+        int base = 0;
+        if (lane_id() == 0 && mask) base = atomicAdd(&s_nsel, __popcll(mask));
+        base = __shfl(base, 0, kWave);
+        if (in) sel[base + __popcll(mask & lanemask_lt())] = i;
+      }
+      __syncthreads();
+      const int nS = s_nsel;
+      if (nS == 0) continue;  // uniform: no wedge of this item in the chunk
+      int Fall = 0;
+      for (int g0 = 0; g0 < nS; g0 += kHeavyGroup) {
+        const int nG = min(kHeavyGroup, nS - g0);
+        for (int j = tid; j < nG; j += kC4HeavyBlock) {
+          const int i = sel[g0 + j];
+          const int p = cur[i];
+          vcur[j] = p;
+          vpre[j] = count_below(g.col2, p, end[i], c1);
+        }
+        __syncthreads();
+        scan_excl<kC4HeavyBlock>(vpre, nG, sums);
+        const int F = vpre[nG];
+        Fall += F;
+        for (int f0 = tid * RUN; f0 < F; f0 += kC4HeavyBlock * RUN) {
+          int j = upper_index_dev<int32_t>(vpre, nG, f0);
+          const int f1 = min(f0 + RUN, F);
+          for (int f = f0; f < f1; f++) {
+            while (vpre[j + 1] <= f) j++;
+            const int d = g.col2[vcur[j] + (f - vpre[j])] - c0;
+            if (packed) atomicAdd(&cnt[d >> 1], (d & 1) ? 65536u : 1u);
+            else atomicAdd(&cnt[d], 1u);
+          }
+        }
+        for (int j = tid; j < nG; j += kC4HeavyBlock) {
+          const int i = sel[g0 + j];
+          const int p = vcur[j] + (vpre[j + 1] - vpre[j]);
+          cur[i] = p;
+          nxt[i] = p < end[i] ? g.col2[p] : INT32_MAX;
+        }
+        __syncthreads();
+      }
+      u64 part = 0;
+      if (nS <= kHeavyGroup && Fall <= kSparseChunk) {
+        // vcur / vpre still describe this chunk's wedges
+        for (int f = tid; f < Fall; f += kC4HeavyBlock) {
+          const int j = upper_index_dev<int32_t>(vpre, nS, f);
+          const int d = g.col2[vcur[j] + (f - vpre[j])] - c0;
+          uint32_t val;
+          if (packed) {
+            const int sh = (d & 1) * 16;
+            val = (atomicAnd(&cnt[d >> 1], ~(0xffffu << sh)) >> sh) & 0xffffu;
+          } else {
+            val = atomicExch(&cnt[d], 0u);
+          }
+          part += choose2(val);
+        }
+      } else {
+        for (int w = tid; w < kChunkWords; w += kC4HeavyBlock) {
+          const uint32_t val = cnt[w];
+          if (val) {
+            cnt[w] = 0;
+            if (packed) part += choose2(val & 0xffffu) + choose2(val >> 16);
+            else part += choose2(val);
+          }
+        }
+      }
+      acc += (u128)part;
+      __syncthreads();
+    }
+  }
+  const u128 s = block_sum_u128(acc, red);
+  if (threadIdx.x == 0 && s) atomic_add_u128(g.c4ni, s);
+}
+
 }  // namespace
+
+int launch_cycles_medium(C4Args g, hipStream_t s) {
+  if (g.nlist <= 0) return GC_OK;
+  const unsigned grid = (unsigned)std::min(g.nlist, 16384);
+  k_c4_medium<<<grid, kMediumBlock, 0, s>>>(g);
+  GC_TRY_HIP(hipGetLastError());
+  return GC_OK;
+}
 
 int launch_cycles_light(C4Args g, bool per_edge, hipStream_t s) {
   if (g.nlist <= 0) return GC_OK;
@@ -233,7 +506,7 @@ int launch_cycles_light(C4Args g, bool per_edge, hipStream_t s) {
 int launch_cycles_heavy(C4Args g, int slots, bool per_edge, hipStream_t s) {
   if (slots <= 0) return GC_OK;
   if (per_edge) k_c4_heavy<true><<<slots, kC4HeavyBlock, 0, s>>>(g);
-  else k_c4_heavy<false><<<slots, kC4HeavyBlock, 0, s>>>(g);
+  else k_c4_heavy_bal<<<slots, kC4HeavyBlock, 0, s>>>(g);
   GC_TRY_HIP(hipGetLastError());
   return GC_OK;
 }

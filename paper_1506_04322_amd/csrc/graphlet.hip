@@ -79,7 +79,10 @@ void alloc_fixed(Arena &a, const Plan &P, Fixed &f) {
   p.tpos = a.take<int32_t>(nnz);
   for (int i = 0; i < kTkBins; i++) p.tk[i] = a.take<int32_t>(n);
   p.c4l = a.take<int32_t>(n);
+  p.c4m = a.take<int32_t>(n);
   p.c4h = a.take<int32_t>(n);
+  // the medium class exists in global mode only
+  p.medium_max = P.per_edge ? kLightWedges : kMediumWedges;
   f.T = a.take<uint32_t>(nnz);
   f.nstep3 = (int)std::min<int64_t>(kStep3Grid, std::max<int64_t>(1, (nnz + 255) / 256));
   f.partials = a.take<u64>((size_t)f.nstep3 * kAcc * 2);
@@ -117,7 +120,7 @@ struct Dyn {
   u64 *gR;
   int32_t *gI;
   u64 *gA;
-  int32_t *gcur, *gbeg;
+  int32_t *gcur, *gbeg, *gnext, *gsel;
   u64 *gacc;
   int4 *items;
   u64 *hkeys, *hkeys_alt;
@@ -131,7 +134,9 @@ void alloc_dyn(Arena &a, const Plan &P, const DynNeed &d, Dyn &y) {
   y.gA = km ? a.take<u64>((size_t)kTkGlobalSlots * 3 * km) : nullptr;
   const size_t lm = (size_t)std::max(d.lmax, 1), sl = (size_t)std::max(d.slots, 1);
   y.gcur = a.take<int32_t>(sl * lm);
-  y.gbeg = P.per_edge ? a.take<int32_t>(sl * lm) : nullptr;
+  y.gbeg = a.take<int32_t>(sl * lm);
+  y.gnext = P.per_edge ? nullptr : a.take<int32_t>(sl * lm);
+  y.gsel = P.per_edge ? nullptr : a.take<int32_t>(sl * lm);
   y.gacc = P.per_edge ? a.take<u64>(sl * lm) : nullptr;
   y.items = a.take<int4>((size_t)std::max<int64_t>(d.items_cap, 1));
   const size_t nh = (size_t)std::max(d.nheavy, 1);
@@ -439,6 +444,12 @@ int run(const gc_csr *G, gc_u128 out17[17], int64_t *per_edge_out, char *ws, siz
   c4.list = pp.c4l;
   c4.nlist = hc.c4_light;
   GC_TRY(launch_cycles_light(c4, P.per_edge, s));
+  if (hc.c4_medium > 0) {
+    C4Args cm = c4;
+    cm.list = pp.c4m;
+    cm.nlist = hc.c4_medium;
+    GC_TRY(launch_cycles_medium(cm, s));
+  }
   ev.record(4, s);
   if (dn.nheavy > 0) {
     c4.items = dy.items;
@@ -446,6 +457,8 @@ int run(const gc_csr *G, gc_u128 out17[17], int64_t *per_edge_out, char *ws, siz
     c4.queue = &pp.acc->queue;
     c4.gcur = dy.gcur;
     c4.gbeg = dy.gbeg;
+    c4.gnext = dy.gnext;
+    c4.gsel = dy.gsel;
     c4.gacc = dy.gacc;
     c4.lmax = std::max(dn.lmax, 1);
     GC_TRY(launch_cycles_heavy(c4, dn.slots, P.per_edge, s));
@@ -495,7 +508,7 @@ int run(const gc_csr *G, gc_u128 out17[17], int64_t *per_edge_out, char *ws, siz
     t.ms[4] = ev.span(5, 6);
     t.ms[5] = ev.span(6, 7);
     t.clique_entries = hc.clique_entries;
-    t.wedges_light = hc.wedges_light;
+    t.wedges_light = hc.wedges_light + hc.wedges_medium;
     t.wedges_heavy = hc.wedges_heavy;
     t.heavy_items = h.nitems;
   }

@@ -36,9 +36,19 @@ __host__ __device__ inline int tk_class(int k) {
 // Light wedge vertices: at most this many wedges (LDS hash of <= 2048 slots).
 constexpr u64 kLightWedges = 1024;
 constexpr int kHashSlots = 2048;
-// Heavy wedge vertices: LDS counter chunk of 128 KiB.
+// Medium wedge vertices (global mode only): one workgroup, LDS hash at load
+// factor <= 1/2.
+constexpr u64 kMediumWedges = 8192;
+constexpr int kMediumSlots = 16384;
+constexpr int kMediumBlock = 1024;
+// A chunk with at most this many wedges is summed and cleared by revisiting
+// its wedges instead of sweeping every counter word.
+constexpr int kSparseChunk = 8192;
+// Heavy wedge vertices: LDS counter chunk of 128 KiB; lower neighbours are
+// measured in groups of kHeavyGroup per chunk.
 constexpr int kChunkWords = 32768;
 constexpr int kC4HeavyBlock = 1024;
+constexpr int kHeavyGroup = 2048;
 // Target wedges per heavy work item.
 constexpr u64 kPieceWork = u64(1) << 21;
 // Concurrent workgroups of the global-memory clique kernel.
@@ -67,11 +77,12 @@ struct Counters {
   int32_t max_ucnt;
   int32_t max_lcnt_heavy;
   int32_t max_deg;
-  int32_t pad[6];
+  int32_t c4_medium;
+  int32_t pad[5];
   u64 wedges_light;
   u64 wedges_heavy;
   u64 clique_entries;
-  u64 pad2;
+  u64 wedges_medium;
 };
 
 __device__ __forceinline__ void flag_err(int32_t *err, int code) { atomicOr(err, 1 << (-code)); }
@@ -94,8 +105,9 @@ struct PrepassArgs {
   // outputs
   int32_t *deg, *order, *rank, *deg2, *rp2, *col2, *lcnt, *ucnt, *ustart, *tpos;
   u64 *rkeys, *rkeys_alt, *ekeys, *ekeys_alt, *W;
-  int32_t *tk[kTkBins], *c4l, *c4h;
-  u64 *esorted;  // set by the prepass: sorted (row << B | col) keys
+  int32_t *tk[kTkBins], *c4l, *c4m, *c4h;
+  u64 medium_max;  // wedges of the largest medium vertex (= light limit: no medium class)
+  u64 *esorted;    // set by the prepass: sorted (row << B | col) keys
 };
 
 // Maximum degree and maximum |U(x)| of a caller CSR (one sync on s).
@@ -149,12 +161,16 @@ struct C4Args {
   const int64_t *nitems;
   u64 *queue;
   int32_t *gcur;  // per slot: cursor per lower neighbour
-  int32_t *gbeg;  // per slot (per-edge): cursor at chunk start
+  int32_t *gbeg;  // per slot: end of each active list (global mode) or
+                  // cursor at chunk start (per-edge mode)
+  int32_t *gnext; // per slot (global mode): next entry of each active list
+  int32_t *gsel;  // per slot (global mode): lists with entries in the chunk
   u64 *gacc;      // per slot (per-edge): credit for edge (x, v)
   int lmax;
 };
 
 int launch_cycles_light(C4Args g, bool per_edge, hipStream_t s);
+int launch_cycles_medium(C4Args g, hipStream_t s);
 int launch_cycles_heavy(C4Args g, int slots, bool per_edge, hipStream_t s);
 
 // ---------------------------------------------------------------- Step 3

@@ -194,8 +194,9 @@ __device__ __forceinline__ void wave_append(bool cond, int32_t x, int32_t *list,
 __global__ __launch_bounds__(256) void k_bins(const int32_t *ucnt, const int32_t *lcnt,
                                               const u64 *W, int64_t n, int32_t *tk0, int32_t *tk1,
                                               int32_t *tk2, int32_t *tk3, int32_t *tk4,
-                                              int32_t *c4l, int32_t *c4h, Counters *cnt) {
-  __shared__ u64 red[2][4];
+                                              int32_t *c4l, int32_t *c4m, int32_t *c4h,
+                                              u64 medium_max, Counters *cnt) {
+  __shared__ u64 red[3][4];
   const int64_t xi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool in = xi < n;
   const int32_t x = (int32_t)xi;
@@ -208,23 +209,29 @@ __global__ __launch_bounds__(256) void k_bins(const int32_t *ucnt, const int32_t
   wave_append(cls == 3, x, tk3, &cnt->tk_cnt[3]);
   wave_append(cls == 4, x, tk4, &cnt->tk_cnt[4]);
   const bool light = w >= 2 && w <= kLightWedges;  // one wedge cannot close a cycle
-  const bool heavy = w > kLightWedges;
+  const bool medium = w > kLightWedges && w <= medium_max;
+  const bool heavy = w > medium_max && w > kLightWedges;
   wave_append(light, x, c4l, &cnt->c4_light);
+  wave_append(medium, x, c4m, &cnt->c4_medium);
   wave_append(heavy, x, c4h, &cnt->c4_heavy);
   int ml = heavy ? lcnt[x] : 0;
   for (int off = 32; off > 0; off >>= 1) ml = max(ml, __shfl_xor(ml, off, kWave));
   if (lane_id() == 0 && ml) atomicMax(&cnt->max_lcnt_heavy, ml);
-  const u64 wl = wave_sum_u64(light ? w : 0), wh = wave_sum_u64(heavy ? w : 0);
+  const u64 wl = wave_sum_u64(light ? w : 0), wm = wave_sum_u64(medium ? w : 0),
+            wh = wave_sum_u64(heavy ? w : 0);
   if (lane_id() == 0) {
     red[0][threadIdx.x / kWave] = wl;
     red[1][threadIdx.x / kWave] = wh;
+    red[2][threadIdx.x / kWave] = wm;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     const u64 a = red[0][0] + red[0][1] + red[0][2] + red[0][3];
     const u64 b = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    const u64 c = red[2][0] + red[2][1] + red[2][2] + red[2][3];
     if (a) atomicAdd(&cnt->wedges_light, a);
     if (b) atomicAdd(&cnt->wedges_heavy, b);
+    if (c) atomicAdd(&cnt->wedges_medium, c);
   }
 }
 
@@ -241,8 +248,21 @@ __global__ void k_heavy_keys(const int32_t *c4h, int nh, const u64 *W, u64 *keys
 
 __device__ __forceinline__ int chunk_span(int nl) { return nl < 65536 ? 2 * kChunkWords : kChunkWords; }
 
-// Pieces of a heavy vertex: y range [0, x) cut into about W / kPieceWork
-// pieces, at most one per LDS chunk.
+// Pieces of a heavy vertex.  Wedge endpoints y crowd toward x (the highest
+// ranks are the highest degrees), so the y range [0, x) is cut from the top
+// in pieces of 1, 1, 2, 4, 8, ... LDS chunks, the last piece taking the rest;
+// at most about W / kPieceWork pieces.
+__device__ __forceinline__ int64_t piece_top(int64_t k) { return k == 0 ? 0 : (int64_t)1 << (k - 1); }
+
+__device__ int64_t piece_count(u64 w, int64_t nchunks) {
+  int64_t S = (int64_t)((w + kPieceWork - 1) / kPieceWork);
+  int64_t need = 1;  // pieces until the doubling sizes cover every chunk
+  while (piece_top(need) < nchunks) need++;
+  if (S > need) S = need;
+  if (S < 1) S = 1;
+  return S;
+}
+
 __global__ void k_heavy_pieces(const u64 *sorted, int nh, const int32_t *c4h, const u64 *W,
                                const int32_t *lcnt, int64_t *pcount) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -250,10 +270,7 @@ __global__ void k_heavy_pieces(const u64 *sorted, int nh, const int32_t *c4h, co
   const int x = c4h[(int)(sorted[s] & 0xffffffffull)];
   const int64_t K = chunk_span(lcnt[x]);
   const int64_t nchunks = ((int64_t)x + K - 1) / K;
-  int64_t S = (int64_t)((W[x] + kPieceWork - 1) / kPieceWork);
-  if (S > nchunks) S = nchunks;
-  if (S < 1) S = 1;
-  pcount[s] = S;
+  pcount[s] = piece_count(W[x], nchunks);
 }
 
 __global__ void k_heavy_expand(const u64 *sorted, int nh, const int32_t *c4h,
@@ -266,9 +283,11 @@ __global__ void k_heavy_expand(const u64 *sorted, int nh, const int32_t *c4h,
   const int64_t nchunks = ((int64_t)x + K - 1) / K;
   const int64_t S = pcount[s], base = poff[s];
   for (int64_t k = 0; k < S; k++) {
-    const int64_t c0 = nchunks * k / S, c1 = nchunks * (k + 1) / S;
-    const int ya = (int)(c0 * K);
-    const int yb = (int)(c1 * K < x ? c1 * K : x);
+    const int64_t hi = nchunks - piece_top(k);
+    int64_t lo = k == S - 1 ? 0 : nchunks - piece_top(k + 1);
+    if (lo < 0) lo = 0;
+    const int ya = (int)(lo * K);
+    const int yb = (int)(hi * K < x ? hi * K : x);
     items[base + k] = make_int4(x, ya, yb, 0);
   }
   if (s == nh - 1) *nitems = base + S;
@@ -360,7 +379,8 @@ int run_prepass(PrepassArgs &p, Arena &a, hipStream_t s) {
   k_wedges<<<grid1d(nnz, 256), 256, 0, s>>>(p.esorted, p.col2, p.rp2, p.tpos, p.ucnt, nnz, B, p.W,
                                             &p.cnt->clique_entries);
   k_bins<<<grid1d(n, 256), 256, 0, s>>>(p.ucnt, p.lcnt, p.W, n, p.tk[0], p.tk[1], p.tk[2],
-                                        p.tk[3], p.tk[4], p.c4l, p.c4h, p.cnt);
+                                        p.tk[3], p.tk[4], p.c4l, p.c4m, p.c4h, p.medium_max,
+                                        p.cnt);
   GC_TRY_HIP(hipGetLastError());
   return GC_OK;
 }
