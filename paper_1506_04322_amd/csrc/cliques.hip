@@ -79,12 +79,12 @@ template <int BLOCK, int KCAP, int HS>
 __global__ __launch_bounds__(BLOCK) void k_tk_up(TkArgs g) {
   constexpr int WC = (KCAP + 63) / 64;
   constexpr int RWORDS = 32 * WC * (WC + 1);  // tri_off(64 WC, WC)
-  constexpr int RUN = 4;                       // consecutive entries per thread
-  __shared__ int32_t U[KCAP], V[KCAP], P[KCAP + 1], H[HS], sums[BLOCK];
+  constexpr int RUN = 8;                       // consecutive entries per thread
+  __shared__ int32_t U[KCAP], V[KCAP], P[KCAP + 1], rid[KCAP], H[HS], sums[BLOCK];
   __shared__ uint32_t colcnt[KCAP];
   __shared__ u64 R[RWORDS];
   __shared__ u64 red[32];
-  __shared__ int next;
+  __shared__ int next, nrows;
   const int tid = threadIdx.x;
   u128 k4acc = 0;
   for (int it = blockIdx.x; it < g.nlist; it += gridDim.x) {
@@ -92,8 +92,8 @@ __global__ __launch_bounds__(BLOCK) void k_tk_up(TkArgs g) {
     const int k = g.ucnt[u];
     const int base = g.ustart[u];
     const int W = (k + 63) >> 6;
-    int hs = 64;
-    while (hs < 2 * k) hs <<= 1;
+    int hs = 64;  // load factor <= 1/4: most misses stop at the first slot
+    while (hs < 4 * k && hs < HS) hs <<= 1;
     const int hbits = __ffs(hs) - 1;
     const uint32_t mask = (uint32_t)hs - 1;
     const int rwords = tri_off(k, W);
@@ -103,50 +103,92 @@ __global__ __launch_bounds__(BLOCK) void k_tk_up(TkArgs g) {
     }
     for (int h = tid; h < hs; h += BLOCK) H[h] = 0;
     for (int w = tid; w < rwords; w += BLOCK) R[w] = 0;
-    if (tid == 0) next = 0;
-    __syncthreads();
-    for (int i = tid; i < k; i += BLOCK) {
-      const int v = U[i];
-      V[i] = g.ustart[v];
-      P[i] = g.ucnt[v];
-      uint32_t h = hslot(v, hbits);
-      while (atomicCAS(&H[h], 0, i + 1) != 0) h = (h + 1) & mask;
+    if (tid == 0) {
+      next = 0;
+      nrows = 0;
     }
     __syncthreads();
-    block_scan_excl<BLOCK>(P, k, sums);
-    const int total = P[k];
-    // Build: every entry x of U(U_i) that lies in U(u) is a triangle.
+    // hash U(u); keep only the rows whose vertex has upper neighbours
+    for (int i0 = 0; i0 < k; i0 += BLOCK) {
+      const int i = i0 + tid;
+      int len = 0, v = 0;
+      if (i < k) {
+        v = U[i];
+        len = g.ucnt[v];
+        uint32_t h = hslot(v, hbits);
+        while (atomicCAS(&H[h], 0, i + 1) != 0) h = (h + 1) & mask;
+      }
+      const bool keep = len > 0;
+      const u64 m = __ballot(keep);
+      int b = 0;
+      if (lane_id() == 0 && m) b = atomicAdd(&nrows, __popcll(m));
+      b = __shfl(b, 0, kWave);
+      if (keep) {
+        const int o = b + __popcll(m & lanemask_lt());
+        rid[o] = i;
+        V[o] = g.ustart[v];
+        P[o] = len;
+      }
+    }
+    __syncthreads();
+    const int nr = nrows;
+    block_scan_excl<BLOCK>(P, nr, sums);
+    const int total = P[nr];
+    // Build: every entry x of U(U_i) that lies in U(u) is a triangle.  Each
+    // thread takes RUN consecutive entries: positions first, then all loads,
+    // then the LDS work, so RUN reads are in flight per thread.
     for (int t0 = tid * RUN; t0 < total; t0 += BLOCK * RUN) {
-      int i = upper_index_dev<int32_t>(P, k, t0);
-      const int t1 = min(t0 + RUN, total);
-      for (int t = t0; t < t1; t++) {
-        while (P[i + 1] <= t) i++;
-        const int pos = V[i] + (t - P[i]);
-        const int j = hfind(H, U, mask, hbits, g.col2[pos]);
+      int i = upper_index_dev<int32_t>(P, nr, t0);
+      int pos[RUN], row[RUN], xv[RUN];
+#pragma unroll
+      for (int r = 0; r < RUN; r++) {
+        const int t = t0 + r;
+        pos[r] = -1;
+        if (t < total) {
+          while (P[i + 1] <= t) i++;
+          pos[r] = V[i] + (t - P[i]);
+          row[r] = rid[i];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < RUN; r++) xv[r] = pos[r] >= 0 ? g.col2[pos[r]] : -1;
+#pragma unroll
+      for (int r = 0; r < RUN; r++) {
+        if (pos[r] < 0) continue;
+        const int j = hfind(H, U, mask, hbits, xv[r]);
         if (j >= 0) {
-          atomicOr(&R[tri_off(i, W) + (j >> 6) - (i >> 6)], 1ull << (j & 63));
+          const int ir = row[r];
+          atomicOr(&R[tri_off(ir, W) + (j >> 6) - (ir >> 6)], 1ull << (j & 63));
           atomicAdd(&colcnt[j], 1u);
-          atomicAdd(&g.T[pos], 1u);
+          atomicAdd(&g.T[pos[r]], 1u);
         }
       }
     }
     __syncthreads();
     // |Tri| of edges (u, U_i); 4-cliques u < U_i < U_j < U_l, each once.
+    // Row i stays in registers (word z of the row, zero below word qi), so
+    // each AND reads only row j from LDS.
     u64 acc = 0;
     for (int i = atomicAdd(&next, 1); i < k; i = atomicAdd(&next, 1)) {
       const u64 *Ri = R + tri_off(i, W);
       const int qi = i >> 6;
+      u64 ri[WC];
+#pragma unroll
+      for (int z = 0; z < WC; z++) ri[z] = (z >= qi && z < W) ? Ri[z - qi] : 0ull;
       uint32_t c = colcnt[i];
-      for (int w = qi; w < W; w++) c += (uint32_t)__popcll(Ri[w - qi]);
+#pragma unroll
+      for (int z = 0; z < WC; z++) c += (uint32_t)__popcll(ri[z]);
       if (c) atomicAdd(&g.T[base + i], c);
-      for (int w = qi; w < W; w++) {
-        u64 bits = Ri[w - qi];
+#pragma unroll
+      for (int w = 0; w < WC; w++) {
+        u64 bits = ri[w];
         while (bits) {
           const int j = (w << 6) + __ffsll((long long)bits) - 1;
           bits &= bits - 1;
-          const u64 *Rj = R + tri_off(j, W);
-          const int qj = j >> 6;
-          for (int z = qj; z < W; z++) acc += (u64)__popcll(Ri[z - qi] & Rj[z - qj]);
+          const u64 *Rj = R + tri_off(j, W) - (j >> 6);  // Rj[z] = word z of row j
+#pragma unroll
+          for (int z = w; z < WC; z++)
+            if (z < W) acc += (u64)__popcll(ri[z] & Rj[z]);
         }
       }
     }
@@ -292,10 +334,10 @@ int launch_cliques(TkArgs g, int bin, bool per_edge, hipStream_t s) {
   auto grid = [&](int cap) { return (unsigned)std::min(g.nlist, cap); };
   if (!per_edge) {
     switch (bin) {
-      case 0: k_tk_up<64, kTkLim0, 128><<<grid(65536), 64, 0, s>>>(g); break;
-      case 1: k_tk_up<256, kTkLim1, 512><<<grid(16384), 256, 0, s>>>(g); break;
-      case 2: k_tk_up<256, kTkLim2, 1024><<<grid(8192), 256, 0, s>>>(g); break;
-      case 3: k_tk_up<512, kTkLim3, 4096><<<grid(4096), 512, 0, s>>>(g); break;
+      case 0: k_tk_up<64, kTkLim0, 256><<<grid(65536), 64, 0, s>>>(g); break;
+      case 1: k_tk_up<256, kTkLim1, 1024><<<grid(16384), 256, 0, s>>>(g); break;
+      case 2: k_tk_up<256, kTkLim2, 2048><<<grid(8192), 256, 0, s>>>(g); break;
+      case 3: k_tk_up<512, kTkLim3, 8192><<<grid(4096), 512, 0, s>>>(g); break;
       default: k_tk_global<256, false><<<grid(kTkGlobalSlots), 256, 0, s>>>(g); break;
     }
   } else {

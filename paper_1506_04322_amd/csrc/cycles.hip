@@ -354,7 +354,7 @@ __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
   __shared__ int32_t vpre[kHeavyGroup + 1], vcur[kHeavyGroup], sums[kC4HeavyBlock / kWave + 1];
   __shared__ u64 red[32];
   __shared__ int s_item, s_nact, s_nsel;
-  constexpr int RUN = 4;
+  constexpr int RUN = 8;
   const int tid = threadIdx.x;
   const int64_t nitems = *g.nitems;
   int32_t *cur = g.gcur + (size_t)blockIdx.x * g.lmax;
@@ -435,10 +435,22 @@ __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
         Fall += F;
         for (int f0 = tid * RUN; f0 < F; f0 += kC4HeavyBlock * RUN) {
           int j = upper_index_dev<int32_t>(vpre, nG, f0);
-          const int f1 = min(f0 + RUN, F);
-          for (int f = f0; f < f1; f++) {
-            while (vpre[j + 1] <= f) j++;
-            const int d = g.col2[vcur[j] + (f - vpre[j])] - c0;
+          int pos[RUN], yv[RUN];
+#pragma unroll
+          for (int r = 0; r < RUN; r++) {
+            const int f = f0 + r;
+            pos[r] = -1;
+            if (f < F) {
+              while (vpre[j + 1] <= f) j++;
+              pos[r] = vcur[j] + (f - vpre[j]);
+            }
+          }
+#pragma unroll
+          for (int r = 0; r < RUN; r++) yv[r] = pos[r] >= 0 ? g.col2[pos[r]] : 0;
+#pragma unroll
+          for (int r = 0; r < RUN; r++) {
+            if (pos[r] < 0) continue;
+            const int d = yv[r] - c0;
             if (packed) atomicAdd(&cnt[d >> 1], (d & 1) ? 65536u : 1u);
             else atomicAdd(&cnt[d], 1u);
           }
