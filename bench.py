@@ -7,7 +7,11 @@ counts, CSR resident in HBM before the timed region.  One step = one
 graphlet_count call (prepass, Steps 1-4, result on the host).
 
 Prints one JSON line (the last line of stdout).  Other workloads:
-  --workload er | cl | batch
+  --workload er | cl       the other single-graph configurations
+  --workload batch         8192 small graphs in one batched call, against one
+                           plain call per graph
+  --workload serve         Poisson request stream through the serving loop,
+                           against plain per-request launches
 """
 from __future__ import annotations
 
@@ -152,6 +156,25 @@ def run_batch(args, torch, gl):
         gl.graphlet_count_batched(no, rp, col, out=out)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) / args.steps * 1e3
+    # baseline: one plain graphlet_count launch per graph, on a sample
+    import numpy as np
+
+    rng = np.random.default_rng(0)
+    sample = rng.choice(b.graphs, size=min(args.per_graph_sample, b.graphs), replace=False)
+    dev_graphs = []
+    for i in sample:
+        g = b.graph(int(i))
+        dev_graphs.append((torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col).to(dev), g.n))
+    for rp1, col1, n1 in dev_graphs[:8]:
+        gl.graphlet_count(rp1, col1, n1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for rp1, col1, n1 in dev_graphs:
+        gl.graphlet_count(rp1, col1, n1)
+    torch.cuda.synchronize()
+    per_graph_s = (time.perf_counter() - t1) / len(dev_graphs)
+    log(f"[bench] batched {ms:.2f} ms for {b.graphs} graphs; per-graph launches "
+        f"{per_graph_s * 1e3:.3f} ms/graph")
     return {
         "metric": "batched graphs/sec", "value": b.graphs / (ms / 1e3), "unit": "graphs/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -159,6 +182,77 @@ def run_batch(args, torch, gl):
         "dtype": "int64 (exact integer)", "data": "synthetic",
         "config": {"workload": "batch8192", "graphs": b.graphs, "csr_sha256": b.sha256(),
                    "params": C.BATCH},
+        "per_graph_launches": {"graphs_per_s": 1.0 / per_graph_s,
+                               "sample": f"{len(dev_graphs)} graphs of the batch, one "
+                                         "graphlet_count call each, CSR resident"},
+        "speedup_vs_per_graph": (b.graphs / (ms / 1e3)) * per_graph_s,
+    }
+
+
+def serve_trace(gl, graphs, trace, slots, budget):
+    """Replays (arrival_s, pool index) against a server; returns its stats."""
+    with gl.Server(budget_bytes=budget, slots=slots) as srv:
+        t0 = time.perf_counter()
+        ids = []
+        for at, gi in trace:
+            delay = at - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            g = graphs[gi]
+            ids.append(srv.submit(g.n, g.row_ptr, g.col))
+        for i in ids:
+            srv.wait(i)
+        st = srv.stats()
+    return st
+
+
+def run_serve(args, torch, gl):
+    """Poisson arrivals at 200 req/s of graphs with m log-uniform in [1e3, 2e6]
+    (half Chung-Lu exponent 2.3, half ER, mean degree 10).  A pool of
+    distinct graphs drawn from the same trace distribution stands in for the
+    request stream (each request is counted independently, so repeats of a
+    pool graph cost the same as new graphs).  Served: 4 slots (streams) with
+    admission by device-memory footprint.  Baseline: the same trace through
+    one slot, i.e. plain per-request launches in arrival order."""
+    import graphgen.configs as C
+
+    nreq = args.requests
+    pool_n = min(args.pool, nreq)
+    reqs = C.serve_requests(nreq)
+    t0 = time.time()
+    graphs = [C.serve_graph(k, n, m, sd) for (_, k, n, m, sd) in reqs[:pool_n]]
+    log(f"[bench] serve pool: {pool_n} graphs, {sum(g.m for g in graphs)} edges "
+        f"in {time.time() - t0:.1f}s; {nreq} requests")
+    trace = [(reqs[i][0], i % pool_n) for i in range(nreq)]
+    budget = 64 << 30
+    # warm up the library and the stream-ordered allocator
+    serve_trace(gl, graphs, [(0.0, i) for i in range(min(8, pool_n))], 4, budget)
+    served = serve_trace(gl, graphs, trace, 4, budget)
+    log(f"[bench] served: {served['graphs_per_s']:.1f} graphs/s p50 {served['p50_ms']:.2f} ms "
+        f"p99 {served['p99_ms']:.2f} ms")
+    plain = serve_trace(gl, graphs, trace, 1, budget)
+    log(f"[bench] per-request plain: {plain['graphs_per_s']:.1f} graphs/s "
+        f"p50 {plain['p50_ms']:.2f} ms p99 {plain['p99_ms']:.2f} ms")
+    # saturated: every request at time 0
+    sat = serve_trace(gl, graphs, [(0.0, i % pool_n) for i in range(nreq)], 4, budget)
+    sat1 = serve_trace(gl, graphs, [(0.0, i % pool_n) for i in range(nreq)], 1, budget)
+    log(f"[bench] saturated: served {sat['graphs_per_s']:.1f} graphs/s, plain "
+        f"{sat1['graphs_per_s']:.1f} graphs/s")
+    keep = ("completed", "failed", "p50_ms", "p99_ms", "mean_ms", "graphs_per_s", "edges_per_s",
+            "bytes_peak", "elapsed_s")
+    return {
+        "metric": "served graphs/sec (Poisson 200 req/s) with p50/p99 latency",
+        "value": served["graphs_per_s"], "unit": "graphs/s", "n_gpus": 1,
+        "steps": nreq, "warmup": 8, "ms_per_step": served["mean_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u128 (exact integer)", "data": "synthetic",
+        "config": {"workload": "serve", "requests": nreq, "pool_graphs": pool_n,
+                   "params": C.SERVE, "slots": 4, "budget_bytes": budget},
+        "p50_ms": served["p50_ms"], "p99_ms": served["p99_ms"],
+        "served": {k: served[k] for k in keep},
+        "per_request_plain": {k: plain[k] for k in keep},
+        "saturated_served": {k: sat[k] for k in keep},
+        "saturated_plain": {k: sat1[k] for k in keep},
     }
 
 
@@ -167,7 +261,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rmat22", choices=["rmat22", "er", "cl", "batch"])
+    ap.add_argument("--workload", default="rmat22",
+                    choices=["rmat22", "er", "cl", "batch", "serve"])
+    ap.add_argument("--requests", type=int, default=1000, help="serve: trace length")
+    ap.add_argument("--pool", type=int, default=96, help="serve: distinct graphs")
+    ap.add_argument("--per-graph-sample", type=int, default=256,
+                    help="batch: graphs timed with one plain launch each")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -185,6 +284,8 @@ def main():
     gl.load()
     if args.workload == "batch":
         res = run_batch(args, torch, gl)
+    elif args.workload == "serve":
+        res = run_serve(args, torch, gl)
     else:
         res = run_single(args, torch, gl)
     print(json.dumps(res), flush=True)

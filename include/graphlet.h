@@ -162,6 +162,55 @@ typedef struct gc_timing {
 void graphlet_timing_enable(int on);
 int graphlet_last_timing(gc_timing *out);
 
+/*
+ * Serving loop (continuous batching).  Graphs are submitted from HOST memory;
+ * each is copied into the server, admitted onto the device when a worker
+ * slot is free and its footprint (CSR + workspace bound) fits the remaining
+ * device-memory budget, counted with graphlet_count on the worker's own HIP
+ * stream, and its CSR freed when its counts are on the host.  Requests that
+ * arrive while others run are admitted as slots and memory free up, so the
+ * work of several requests overlaps on the device; a request's result is the
+ * same as a standalone graphlet_count of its graph.
+ *   gc_server_create   budget in bytes of device memory, slots = concurrent
+ *                      requests (1..64, one stream each), flags as for
+ *                      graphlet_count (GC_VALIDATE checks every request).
+ *                      NULL on bad arguments (gc_server_last_error()).
+ *   gc_server_submit   host CSR (gc_csr contract; copied before returning).
+ *                      Returns a request id > 0, or GC_EINVAL for a malformed
+ *                      CSR, or GC_ENOMEM when the graph alone exceeds the
+ *                      budget.  Rejected requests never reach the device.
+ *   gc_server_poll     1 done (out_counts filled, latency = completion minus
+ *                      submission, ms), 0 still pending or running, < 0 the
+ *                      request failed (its error code; others are unaffected)
+ *   gc_server_wait     as poll, blocking until the request ends
+ *   gc_server_cancel   a pending request is dropped; a running one finishes
+ *                      on the device and its result is discarded
+ *   gc_server_release  forgets a finished request (its id becomes invalid)
+ *   gc_server_stats    counters, latency percentiles over completed requests
+ *                      and throughput since creation or the last reset
+ *   gc_server_destroy  cancels pending requests, waits for running ones
+ * Calls may come from any thread.  The server owns its copies of submitted
+ * graphs; it keeps no caller pointer.
+ */
+typedef struct gc_server gc_server;
+typedef struct gc_serve_stats {
+  int64_t submitted, completed, failed, rejected, cancelled, pending, running;
+  size_t bytes_in_use, bytes_peak, budget;
+  double p50_ms, p99_ms, mean_ms, elapsed_s, graphs_per_s, edges_per_s;
+} gc_serve_stats;
+
+gc_server *gc_server_create(size_t hbm_budget, int slots, uint32_t flags);
+int64_t gc_server_submit(gc_server *s, int64_t n, int64_t nnz, const int32_t *row_ptr,
+                         const int32_t *col);
+int gc_server_poll(gc_server *s, int64_t id, gc_u128 out_counts[17], double *latency_ms);
+int gc_server_wait(gc_server *s, int64_t id, gc_u128 out_counts[17], double *latency_ms);
+int gc_server_cancel(gc_server *s, int64_t id);
+int gc_server_release(gc_server *s, int64_t id);
+int gc_server_stats(gc_server *s, gc_serve_stats *out);
+int gc_server_reset_stats(gc_server *s);
+void gc_server_destroy(gc_server *s);
+const char *gc_server_last_error(void);
+
 /* Message of the calling thread's most recent error ("" if none). */
 const char *graphlet_last_error(void);
 

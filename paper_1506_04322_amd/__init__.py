@@ -60,7 +60,26 @@ EXPORTS = [
     "graphlet_version",
     "graphlet_timing_enable",
     "graphlet_last_timing",
+    "gc_server_create",
+    "gc_server_submit",
+    "gc_server_poll",
+    "gc_server_wait",
+    "gc_server_cancel",
+    "gc_server_release",
+    "gc_server_stats",
+    "gc_server_reset_stats",
+    "gc_server_destroy",
+    "gc_server_last_error",
 ]
+
+
+class _ServeStats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in
+                ("submitted", "completed", "failed", "rejected", "cancelled", "pending",
+                 "running")] + \
+               [(name, ctypes.c_size_t) for name in ("bytes_in_use", "bytes_peak", "budget")] + \
+               [(name, ctypes.c_double) for name in
+                ("p50_ms", "p99_ms", "mean_ms", "elapsed_s", "graphs_per_s", "edges_per_s")]
 
 PHASES = ["prepass", "cliques", "cyc_light", "cyc_heavy", "per_edge", "step3"]
 
@@ -95,6 +114,24 @@ def load():
     lib.graphlet_timing_enable.restype = None
     lib.graphlet_last_timing.argtypes = [ctypes.POINTER(_Timing)]
     lib.graphlet_last_timing.restype = ctypes.c_int
+    lib.gc_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.c_uint32]
+    lib.gc_server_create.restype = ctypes.c_void_p
+    lib.gc_server_submit.argtypes = [P, ctypes.c_int64, ctypes.c_int64, P, P]
+    lib.gc_server_submit.restype = ctypes.c_int64
+    for f in (lib.gc_server_poll, lib.gc_server_wait):
+        f.argtypes = [P, ctypes.c_int64, ctypes.POINTER(_U128), ctypes.POINTER(ctypes.c_double)]
+        f.restype = ctypes.c_int
+    for f in (lib.gc_server_cancel, lib.gc_server_release):
+        f.argtypes = [P, ctypes.c_int64]
+        f.restype = ctypes.c_int
+    lib.gc_server_stats.argtypes = [P, ctypes.POINTER(_ServeStats)]
+    lib.gc_server_stats.restype = ctypes.c_int
+    lib.gc_server_reset_stats.argtypes = [P]
+    lib.gc_server_reset_stats.restype = ctypes.c_int
+    lib.gc_server_destroy.argtypes = [P]
+    lib.gc_server_destroy.restype = None
+    lib.gc_server_last_error.argtypes = []
+    lib.gc_server_last_error.restype = ctypes.c_char_p
     _lib = lib
     return lib
 
@@ -207,3 +244,79 @@ def graphlet_last_timing() -> dict:
     d.update(clique_entries=int(t.clique_entries), wedges_light=int(t.wedges_light),
              wedges_heavy=int(t.wedges_heavy), heavy_items=int(t.heavy_items))
     return d
+
+
+class Server:
+    """Continuous-batching server over the C ABI (gc_server_*).
+
+    submit() takes host numpy CSR arrays and returns a request id; wait() /
+    poll() return the 17 counts (python ints) and the latency in ms.
+    """
+
+    def __init__(self, budget_bytes: int, slots: int = 4, validate: bool = False):
+        self._lib = load()
+        h = self._lib.gc_server_create(int(budget_bytes), int(slots),
+                                       GC_VALIDATE if validate else 0)
+        if not h:
+            raise GraphletError(-1, self._lib.gc_server_last_error().decode())
+        self._h = h
+
+    def submit(self, n: int, row_ptr, col) -> int:
+        import numpy as np
+
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        c = np.ascontiguousarray(col, dtype=np.int32)
+        rid = self._lib.gc_server_submit(self._h, int(n), int(c.shape[0]), rp.ctypes.data,
+                                         c.ctypes.data if c.shape[0] else None)
+        if rid < 0:
+            raise GraphletError(int(rid), self._lib.gc_server_last_error().decode())
+        return int(rid)
+
+    def _result(self, fn, rid):
+        out = (_U128 * 17)()
+        lat = ctypes.c_double(0.0)
+        rc = fn(self._h, int(rid), out, ctypes.byref(lat))
+        if rc < 0:
+            raise GraphletError(rc, self._lib.gc_server_last_error().decode())
+        if rc == 0:
+            return None
+        return [int(o.lo) | (int(o.hi) << 64) for o in out], float(lat.value)
+
+    def poll(self, rid: int):
+        """(counts, latency_ms) if finished, None if not; raises if it failed."""
+        return self._result(self._lib.gc_server_poll, rid)
+
+    def wait(self, rid: int):
+        """(counts, latency_ms) once the request ends; raises if it failed."""
+        return self._result(self._lib.gc_server_wait, rid)
+
+    def cancel(self, rid: int) -> None:
+        self._lib.gc_server_cancel(self._h, int(rid))
+
+    def release(self, rid: int) -> None:
+        self._lib.gc_server_release(self._h, int(rid))
+
+    def stats(self) -> dict:
+        st = _ServeStats()
+        self._lib.gc_server_stats(self._h, ctypes.byref(st))
+        return {name: getattr(st, name) for name, _ in _ServeStats._fields_}
+
+    def reset_stats(self) -> None:
+        self._lib.gc_server_reset_stats(self._h)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.gc_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

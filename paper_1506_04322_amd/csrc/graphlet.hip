@@ -589,6 +589,20 @@ int validate(const gc_csr *g, hipStream_t s) {
 
 }  // namespace
 
+// Workspace bound from host-side maxima (used by the server's admission).
+size_t workspace_bound(int64_t n, int64_t nnz, int max_deg, int max_ucnt, bool per_edge) {
+  if (n == 0 || nnz == 0) return 256;
+  gc_csr g{n, nnz, nullptr, nullptr};
+  const Plan P = plan_of(&g, per_edge);
+  Arena a;
+  Fixed f;
+  alloc_fixed(a, P, f);
+  Arena b;
+  Dyn d;
+  alloc_dyn(b, P, dyn_bound(P, max_deg, max_ucnt), d);
+  return a.peak + b.peak + 1024;
+}
+
 size_t workspace_size(const gc_csr *g, int per_edge, hipStream_t s, int *rc) {
   *rc = check_args(g);
   if (*rc) return 0;

@@ -1,0 +1,422 @@
+// Serving loop: graphs of mixed sizes submitted from host memory, admitted
+// onto the device by HBM footprint, counted concurrently on several streams.
+//
+// Continuous batching: a request is admitted as soon as a worker slot is free
+// and the device-memory budget can hold its footprint (CSR + workspace bound);
+// requests that arrive while others are running are admitted as earlier ones
+// finish and release their memory, so the work of several requests overlaps
+// on the device.  Admission is first-come-first-served, but a request that
+// does not fit yet does not block a later one that does.
+//
+// Each request's CSR stays resident on the device from admission until its
+// counts are on the host; each request runs the same graphlet_count path as
+// a standalone call, so its result does not depend on what else is running.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "common.h"
+
+namespace gc {
+size_t workspace_bound(int64_t n, int64_t nnz, int max_deg, int max_ucnt, bool per_edge);
+}
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+enum State { PENDING = 0, RUNNING = 1, DONE = 2, FAILED = 3, CANCELLED = 4 };
+
+struct Request {
+  int64_t id = 0;
+  int64_t n = 0, nnz = 0;
+  std::vector<int32_t> rp, col;
+  size_t footprint = 0;
+  State state = PENDING;
+  bool cancel = false;
+  int rc = 0;
+  std::string err;
+  gc_u128 out[17];
+  Clock::time_point t_submit, t_start, t_done;
+};
+
+}  // namespace
+
+struct gc_server {
+  size_t budget = 0;
+  size_t in_use = 0;
+  size_t peak = 0;
+  uint32_t flags = 0;
+  int device = 0;
+  int slots = 0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Request *> pending;
+  std::unordered_map<int64_t, Request *> all;
+  std::vector<std::thread> workers;
+  int64_t next_id = 1;
+  bool stop = false;
+  int running = 0;
+  // statistics since the last reset
+  int64_t submitted = 0, completed = 0, failed = 0, rejected = 0, cancelled = 0;
+  int64_t edges_done = 0;
+  std::vector<double> latencies;
+  Clock::time_point t_first, t_last;
+  bool any = false;
+};
+
+namespace {
+
+thread_local std::string t_srv_err;
+
+void worker_main(gc_server *S) {
+  (void)hipSetDevice(S->device);
+  hipStream_t st = nullptr;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
+  while (true) {
+    Request *r = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      while (true) {
+        if (S->stop) break;
+        // first pending request, in order, that fits the remaining budget
+        for (auto it = S->pending.begin(); it != S->pending.end(); ++it) {
+          if (S->in_use + (*it)->footprint <= S->budget) {
+            r = *it;
+            S->pending.erase(it);
+            break;
+          }
+        }
+        if (r) break;
+        S->cv_work.wait(lk);
+      }
+      if (!r) break;
+      S->in_use += r->footprint;
+      S->peak = std::max(S->peak, S->in_use);
+      S->running++;
+      r->state = RUNNING;
+      r->t_start = Clock::now();
+    }
+    // run outside the lock
+    int rc = GC_OK;
+    std::string err;
+    int32_t *d_rp = nullptr, *d_col = nullptr;
+    hipError_t e = hipMallocAsync((void **)&d_rp, sizeof(int32_t) * (r->n + 1), st);
+    if (e == hipSuccess && r->nnz > 0)
+      e = hipMallocAsync((void **)&d_col, sizeof(int32_t) * r->nnz, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d_rp, r->rp.data(), sizeof(int32_t) * (r->n + 1), hipMemcpyHostToDevice,
+                         st);
+    if (e == hipSuccess && r->nnz > 0)
+      e = hipMemcpyAsync(d_col, r->col.data(), sizeof(int32_t) * r->nnz, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) {
+      rc = e == hipErrorOutOfMemory ? GC_ENOMEM : GC_EHIP;
+      err = hipGetErrorString(e);
+    } else {
+      gc_csr g{r->n, r->nnz, d_rp, d_col};
+      rc = graphlet_count(&g, r->out, nullptr, nullptr, 0, st, S->flags);
+      if (rc != GC_OK) err = graphlet_last_error();
+    }
+    if (d_col) (void)hipFreeAsync(d_col, st);
+    if (d_rp) (void)hipFreeAsync(d_rp, st);
+    (void)hipStreamSynchronize(st);
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->in_use -= r->footprint;
+      S->running--;
+      r->t_done = Clock::now();
+      r->rc = rc;
+      r->err = err;
+      r->rp.clear();
+      r->rp.shrink_to_fit();
+      r->col.clear();
+      r->col.shrink_to_fit();
+      if (r->cancel) {
+        r->state = CANCELLED;
+        S->cancelled++;
+      } else if (rc == GC_OK) {
+        r->state = DONE;
+        S->completed++;
+        S->edges_done += r->nnz / 2;
+        S->latencies.push_back(
+            std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count());
+        S->t_last = r->t_done;
+      } else {
+        r->state = FAILED;
+        S->failed++;
+      }
+    }
+    S->cv_done.notify_all();
+    S->cv_work.notify_all();
+  }
+  if (st) (void)hipStreamDestroy(st);
+}
+
+double percentile(std::vector<double> v, double q) {
+  if (v.empty()) return 0.0;
+  std::sort(v.begin(), v.end());
+  const double pos = q * (double)(v.size() - 1);
+  const size_t lo = (size_t)pos;
+  const size_t hi = std::min(lo + 1, v.size() - 1);
+  return v[lo] + (v[hi] - v[lo]) * (pos - (double)lo);
+}
+
+// Maximum degree and maximum number of later neighbours under the
+// (degree, id) order, from a host CSR (O(nnz)); also checks the ids.
+bool host_maxima(int64_t n, const int32_t *rp, const int32_t *col, int *max_deg, int *max_ucnt) {
+  int md = 0, mu = 0;
+  for (int64_t u = 0; u < n; u++) {
+    const int64_t a = rp[u], b = rp[u + 1];
+    if (b < a) return false;
+    md = std::max<int>(md, (int)(b - a));
+  }
+  for (int64_t u = 0; u < n; u++) {
+    const int64_t a = rp[u], b = rp[u + 1];
+    const int64_t du = b - a;
+    int c = 0;
+    for (int64_t j = a; j < b; j++) {
+      const int64_t w = col[j];
+      if (w < 0 || w >= n) return false;
+      const int64_t dw = rp[w + 1] - rp[w];
+      c += (dw > du || (dw == du && w > u)) ? 1 : 0;
+    }
+    mu = std::max(mu, c);
+  }
+  *max_deg = md;
+  *max_ucnt = mu;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gc_server_last_error(void) { return t_srv_err.c_str(); }
+
+gc_server *gc_server_create(size_t hbm_budget, int slots, uint32_t flags) {
+  t_srv_err.clear();
+  if (slots <= 0 || slots > 64 || hbm_budget == 0) {
+    t_srv_err = "slots must be in 1..64 and the budget positive";
+    return nullptr;
+  }
+  gc_server *S = new (std::nothrow) gc_server();
+  if (!S) return nullptr;
+  S->budget = hbm_budget;
+  S->slots = slots;
+  S->flags = flags;
+  if (hipGetDevice(&S->device) != hipSuccess) S->device = 0;
+  try {
+    for (int i = 0; i < slots; i++) S->workers.emplace_back(worker_main, S);
+  } catch (...) {
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->stop = true;
+    }
+    S->cv_work.notify_all();
+    for (auto &t : S->workers) t.join();
+    delete S;
+    t_srv_err = "could not start worker threads";
+    return nullptr;
+  }
+  return S;
+}
+
+int64_t gc_server_submit(gc_server *S, int64_t n, int64_t nnz, const int32_t *row_ptr,
+                         const int32_t *col) {
+  t_srv_err.clear();
+  if (!S || n < 0 || nnz < 0 || (nnz & 1) || n > 2147483646LL || nnz > 2147483646LL ||
+      !row_ptr || (nnz > 0 && !col)) {
+    t_srv_err = "invalid request arguments";
+    if (S) {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->rejected++;
+    }
+    return GC_EINVAL;
+  }
+  if (row_ptr[0] != 0 || row_ptr[n] != nnz) {
+    t_srv_err = "row_ptr does not span [0, nnz]";
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->rejected++;
+    return GC_EINVAL;
+  }
+  int max_deg = 0, max_ucnt = 0;
+  if (!host_maxima(n, row_ptr, col, &max_deg, &max_ucnt)) {
+    t_srv_err = "malformed CSR (row offsets or vertex ids)";
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->rejected++;
+    return GC_EINVAL;
+  }
+  const size_t fp = sizeof(int32_t) * (size_t)(n + 1 + nnz) +
+                    gc::workspace_bound(n, nnz, max_deg, max_ucnt, false) + (1u << 20);
+  Request *r = new (std::nothrow) Request();
+  if (!r) return GC_ENOMEM;
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (fp > S->budget) {
+    delete r;
+    t_srv_err = "graph footprint exceeds the server's device-memory budget";
+    S->rejected++;
+    return GC_ENOMEM;
+  }
+  r->id = S->next_id++;
+  r->n = n;
+  r->nnz = nnz;
+  r->rp.assign(row_ptr, row_ptr + n + 1);
+  if (nnz) r->col.assign(col, col + nnz);
+  r->footprint = fp;
+  r->t_submit = Clock::now();
+  if (!S->any) {
+    S->t_first = r->t_submit;
+    S->any = true;
+  }
+  S->all[r->id] = r;
+  S->pending.push_back(r);
+  S->submitted++;
+  S->cv_work.notify_one();
+  return r->id;
+}
+
+// 1: done (out filled), 0: not finished, < 0: the request's error code.
+static int report(gc_server *S, Request *r, gc_u128 out[17], double *latency_ms) {
+  (void)S;
+  if (r->state == DONE) {
+    if (out) std::memcpy(out, r->out, sizeof(r->out));
+    if (latency_ms)
+      *latency_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
+    return 1;
+  }
+  if (r->state == FAILED) {
+    t_srv_err = r->err;
+    return r->rc < 0 ? r->rc : GC_EINTERNAL;
+  }
+  if (r->state == CANCELLED) {
+    t_srv_err = "cancelled";
+    return GC_EINVAL;
+  }
+  return 0;
+}
+
+int gc_server_poll(gc_server *S, int64_t id, gc_u128 out[17], double *latency_ms) {
+  t_srv_err.clear();
+  if (!S) return GC_EINVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->all.find(id);
+  if (it == S->all.end()) {
+    t_srv_err = "unknown request id";
+    return GC_EINVAL;
+  }
+  return report(S, it->second, out, latency_ms);
+}
+
+int gc_server_wait(gc_server *S, int64_t id, gc_u128 out[17], double *latency_ms) {
+  t_srv_err.clear();
+  if (!S) return GC_EINVAL;
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->all.find(id);
+  if (it == S->all.end()) {
+    t_srv_err = "unknown request id";
+    return GC_EINVAL;
+  }
+  Request *r = it->second;
+  S->cv_done.wait(lk, [&] { return r->state >= DONE; });
+  return report(S, r, out, latency_ms);
+}
+
+int gc_server_cancel(gc_server *S, int64_t id) {
+  t_srv_err.clear();
+  if (!S) return GC_EINVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->all.find(id);
+  if (it == S->all.end()) {
+    t_srv_err = "unknown request id";
+    return GC_EINVAL;
+  }
+  Request *r = it->second;
+  if (r->state == PENDING) {
+    S->pending.erase(std::find(S->pending.begin(), S->pending.end(), r));
+    r->state = CANCELLED;
+    r->rp.clear();
+    r->col.clear();
+    S->cancelled++;
+    S->cv_done.notify_all();
+  } else if (r->state == RUNNING) {
+    r->cancel = true;  // result discarded when the device work ends
+  }
+  return GC_OK;
+}
+
+int gc_server_release(gc_server *S, int64_t id) {
+  if (!S) return GC_EINVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->all.find(id);
+  if (it == S->all.end() || it->second->state < DONE) return GC_EINVAL;
+  delete it->second;
+  S->all.erase(it);
+  return GC_OK;
+}
+
+int gc_server_stats(gc_server *S, gc_serve_stats *o) {
+  if (!S || !o) return GC_EINVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  std::memset(o, 0, sizeof(*o));
+  o->submitted = S->submitted;
+  o->completed = S->completed;
+  o->failed = S->failed;
+  o->rejected = S->rejected;
+  o->cancelled = S->cancelled;
+  o->pending = (int64_t)S->pending.size();
+  o->running = S->running;
+  o->bytes_in_use = S->in_use;
+  o->bytes_peak = S->peak;
+  o->budget = S->budget;
+  o->p50_ms = percentile(S->latencies, 0.50);
+  o->p99_ms = percentile(S->latencies, 0.99);
+  double sum = 0;
+  for (double v : S->latencies) sum += v;
+  o->mean_ms = S->latencies.empty() ? 0.0 : sum / (double)S->latencies.size();
+  if (S->any && S->completed > 0) {
+    const double el = std::chrono::duration<double>(S->t_last - S->t_first).count();
+    o->elapsed_s = el;
+    o->graphs_per_s = el > 0 ? (double)S->completed / el : 0.0;
+    o->edges_per_s = el > 0 ? (double)S->edges_done / el : 0.0;
+  }
+  return GC_OK;
+}
+
+int gc_server_reset_stats(gc_server *S) {
+  if (!S) return GC_EINVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->submitted = S->completed = S->failed = S->rejected = S->cancelled = 0;
+  S->edges_done = 0;
+  S->latencies.clear();
+  S->any = false;
+  S->peak = S->in_use;
+  return GC_OK;
+}
+
+void gc_server_destroy(gc_server *S) {
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+    for (Request *r : S->pending) {
+      r->state = CANCELLED;
+    }
+    S->pending.clear();
+  }
+  S->cv_work.notify_all();
+  for (auto &t : S->workers) t.join();
+  for (auto &kv : S->all) delete kv.second;
+  delete S;
+}
+
+}  // extern "C"

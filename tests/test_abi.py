@@ -14,7 +14,7 @@ def declared_functions():
     with open(os.path.join(ROOT, "include", "graphlet.h")) as f:
         text = f.read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(graphlet_\w+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b((?:graphlet|gc_server)_\w+)\s*\(", text)))
 
 
 def test_header_declares_the_binding_exports():
