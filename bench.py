@@ -138,6 +138,20 @@ def run_single(args, torch, gl):
     return res
 
 
+def plan_device_ms(torch, plan, reps=5):
+    """Device time of one replay, from events on the replay's stream."""
+    st = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = float("inf")
+    for _ in range(reps):
+        a.record(st)
+        plan.run(stream=st)
+        b.record(st)
+        b.synchronize()
+        best = min(best, a.elapsed_time(b))
+    return best
+
+
 def run_batch(args, torch, gl):
     import graphgen.configs as C
 
@@ -148,14 +162,33 @@ def run_batch(args, torch, gl):
     dev = torch.device("cuda:0")
     no, rp, col = (torch.from_numpy(x).to(dev) for x in (b.node_off, b.row_ptr, b.col))
     out = torch.empty((b.graphs, 17), dtype=torch.int64, device=dev)
-    for _ in range(args.warmup):
+    # one-shot calls (plan, direct launches, no capture) for reference
+    gl.graphlet_count_batched(no, rp, col, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
         gl.graphlet_count_batched(no, rp, col, out=out)
+    torch.cuda.synchronize()
+    oneshot_ms = (time.perf_counter() - t0) / 3 * 1e3
+    eager = out.clone()
+    # the measured form: autotuned plan, persistent launch replayed as a HIP graph
+    t0 = time.perf_counter()
+    plan = gl.BatchPlan(no, rp, col, tune=True, out=out)
+    tune_s = time.perf_counter() - t0
+    info = plan.info()
+    log(f"[bench] autotuned in {tune_s:.2f}s: {info}")
+    for _ in range(args.warmup):
+        plan.run()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        gl.graphlet_count_batched(no, rp, col, out=out)
+        plan.run()
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) / args.steps * 1e3
+    if not torch.equal(out, eager):
+        raise SystemExit("batched plan replay differs from the one-shot call")
+    ms_dev = plan_device_ms(torch, plan)
+    plan.close()
     # baseline: one plain graphlet_count launch per graph, on a sample
     import numpy as np
 
@@ -182,6 +215,8 @@ def run_batch(args, torch, gl):
         "dtype": "int64 (exact integer)", "data": "synthetic",
         "config": {"workload": "batch8192", "graphs": b.graphs, "csr_sha256": b.sha256(),
                    "params": C.BATCH},
+        "plan": info, "tune_s": tune_s, "device_ms_per_step": ms_dev,
+        "one_shot_graphs_per_s": b.graphs / (oneshot_ms / 1e3),
         "per_graph_launches": {"graphs_per_s": 1.0 / per_graph_s,
                                "sample": f"{len(dev_graphs)} graphs of the batch, one "
                                          "graphlet_count call each, CSR resident"},

@@ -137,6 +137,56 @@ typedef struct gc_batch {
 int graphlet_count_batched(const gc_batch *b, int64_t *out, void *stream, uint32_t flags);
 
 /*
+ * Batched execution plan, for a batch counted again and again (the same
+ * arrays, possibly with new contents of the same sizes).  Creating a plan
+ * checks the batch (GC_VALIDATE as above) and bins the graphs into size
+ * classes by 64-bit words per adjacency row (a class of W words holds graphs
+ * of at most 64 W vertices; W in 1, 2, 4, 6, 8, 10, 12, 16).  Each class is
+ * counted by one persistent launch sized to fill the device, one workgroup
+ * per graph at a time, costliest graphs first; the launches are captured into
+ * a HIP graph.  With tune != 0 the class set and the workgroup size are
+ * chosen by timing the candidates on this batch (the choice is remembered per
+ * process for batches of the same size profile, and graphlet_count_batched
+ * then uses it too).
+ *   graphlet_batch_plan_create  b, out as for graphlet_count_batched (both
+ *                      must stay valid while the plan lives); *plan receives
+ *                      the plan.  Allocates device and pinned host memory.
+ *                      Returns GC_OK or an error code (then *plan is NULL).
+ *   graphlet_batch_plan_run     replays the captured launches on `stream` and
+ *                      returns when out holds the counts; allocates nothing.
+ *                      GC_EINVAL if a graph outgrew its class since the plan
+ *                      was made.
+ *   graphlet_batch_plan_info    the shape in use.
+ *   graphlet_batch_plan_reshape forces a shape: block 256 or 512 threads, and
+ *                      the classes as a mask (bit W-1 set: a class of W
+ *                      words).  GC_EINVAL if no class holds some graph.
+ *                      Re-reads the graph sizes, so it also re-plans a batch
+ *                      whose graphs changed size (same array lengths).
+ *   graphlet_batch_plan_destroy frees the plan.
+ * One plan must not be run from two threads at once.
+ */
+typedef struct gc_batch_plan gc_batch_plan;
+#define GC_BATCH_MAX_CLASSES 8
+typedef struct gc_batch_plan_info {
+  int block;                                 /* threads per workgroup */
+  int classes;                               /* launches per run */
+  int class_words[GC_BATCH_MAX_CLASSES];     /* words per row of each class */
+  int64_t class_graphs[GC_BATCH_MAX_CLASSES];
+  int class_grid[GC_BATCH_MAX_CLASSES];      /* workgroups of each launch */
+  size_t class_lds[GC_BATCH_MAX_CLASSES];    /* dynamic LDS per workgroup */
+  int candidates;                            /* shapes timed by the autotuner (0: not tuned) */
+  double tuned_ms;                           /* best candidate's time */
+} gc_batch_plan_info;
+
+int graphlet_batch_plan_create(const gc_batch *b, int64_t *out, int tune, void *stream,
+                               uint32_t flags, gc_batch_plan **plan);
+int graphlet_batch_plan_run(gc_batch_plan *plan, void *stream);
+int graphlet_batch_plan_info(const gc_batch_plan *plan, gc_batch_plan_info *info);
+int graphlet_batch_plan_reshape(gc_batch_plan *plan, int block, uint32_t class_words_mask,
+                                void *stream);
+void graphlet_batch_plan_destroy(gc_batch_plan *plan);
+
+/*
  * Diagnostics.  When enabled (per calling thread), graphlet_count records HIP
  * events on its stream at the boundaries of its phases, and the durations of
  * the thread's last call can be read back, together with the amount of

@@ -9,6 +9,8 @@ The entry points mirror include/graphlet.h:
   graphlet_count(row_ptr, col, n, per_edge=False, workspace=None, validate=False)
   graphlet_workspace_size(row_ptr, col, n, per_edge=False)
   graphlet_count_batched(node_off, row_ptr, col)
+  BatchPlan(node_off, row_ptr, col, tune=True).run()   (graphlet_batch_plan_*)
+  Server(budget_bytes, slots)                          (gc_server_*)
   graphlet_last_error()
 """
 from __future__ import annotations
@@ -56,6 +58,11 @@ EXPORTS = [
     "graphlet_workspace_size",
     "graphlet_count",
     "graphlet_count_batched",
+    "graphlet_batch_plan_create",
+    "graphlet_batch_plan_run",
+    "graphlet_batch_plan_info",
+    "graphlet_batch_plan_reshape",
+    "graphlet_batch_plan_destroy",
     "graphlet_last_error",
     "graphlet_version",
     "graphlet_timing_enable",
@@ -80,6 +87,13 @@ class _ServeStats(ctypes.Structure):
                [(name, ctypes.c_size_t) for name in ("bytes_in_use", "bytes_peak", "budget")] + \
                [(name, ctypes.c_double) for name in
                 ("p50_ms", "p99_ms", "mean_ms", "elapsed_s", "graphs_per_s", "edges_per_s")]
+
+class _PlanInfo(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int), ("classes", ctypes.c_int),
+                ("class_words", ctypes.c_int * 8), ("class_graphs", ctypes.c_int64 * 8),
+                ("class_grid", ctypes.c_int * 8), ("class_lds", ctypes.c_size_t * 8),
+                ("candidates", ctypes.c_int), ("tuned_ms", ctypes.c_double)]
+
 
 PHASES = ["prepass", "cliques", "cyc_light", "cyc_heavy", "per_edge", "step3"]
 
@@ -106,6 +120,17 @@ def load():
     lib.graphlet_count.restype = ctypes.c_int
     lib.graphlet_count_batched.argtypes = [ctypes.POINTER(_Batch), P, P, ctypes.c_uint32]
     lib.graphlet_count_batched.restype = ctypes.c_int
+    lib.graphlet_batch_plan_create.argtypes = [ctypes.POINTER(_Batch), P, ctypes.c_int, P,
+                                               ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p)]
+    lib.graphlet_batch_plan_create.restype = ctypes.c_int
+    lib.graphlet_batch_plan_run.argtypes = [P, P]
+    lib.graphlet_batch_plan_run.restype = ctypes.c_int
+    lib.graphlet_batch_plan_info.argtypes = [P, ctypes.POINTER(_PlanInfo)]
+    lib.graphlet_batch_plan_info.restype = ctypes.c_int
+    lib.graphlet_batch_plan_reshape.argtypes = [P, ctypes.c_int, ctypes.c_uint32, P]
+    lib.graphlet_batch_plan_reshape.restype = ctypes.c_int
+    lib.graphlet_batch_plan_destroy.argtypes = [P]
+    lib.graphlet_batch_plan_destroy.restype = None
     lib.graphlet_last_error.argtypes = []
     lib.graphlet_last_error.restype = ctypes.c_char_p
     lib.graphlet_version.argtypes = []
@@ -229,6 +254,79 @@ def graphlet_count_batched(node_off, row_ptr, col, out=None, stream=None, valida
     if rc != 0:
         raise GraphletError(rc, graphlet_last_error())
     return out[:G]
+
+
+class BatchPlan:
+    """A batch counted repeatedly: cost-ordered bins, a persistent launch
+    captured in a HIP graph, optionally autotuned (graphlet_batch_plan_*).
+    The tensors must stay alive and keep their sizes while the plan lives."""
+
+    def __init__(self, node_off, row_ptr, col, tune: bool = True, out=None, stream=None,
+                 validate: bool = False):
+        import torch
+
+        lib = load()
+        _check_dev(node_off, torch.int64, "node_off")
+        _check_dev(row_ptr, torch.int32, "row_ptr")
+        _check_dev(col, torch.int32, "col")
+        self.G = node_off.numel() - 1
+        if out is None:
+            out = torch.empty((max(self.G, 1), 17), dtype=torch.int64, device=node_off.device)
+        self._keep = (node_off, row_ptr, col, out)
+        self.out = out
+        b = _Batch(self.G, node_off.data_ptr(), row_ptr.data_ptr(),
+                   col.data_ptr() if col.numel() else 0)
+        h = ctypes.c_void_p()
+        rc = lib.graphlet_batch_plan_create(ctypes.byref(b), out.data_ptr(), 1 if tune else 0,
+                                            _stream_ptr(stream), GC_VALIDATE if validate else 0,
+                                            ctypes.byref(h))
+        if rc != 0:
+            raise GraphletError(rc, graphlet_last_error())
+        self._h = h.value
+
+    def run(self, stream=None):
+        """Replays the captured launch; returns the [G, 17] int64 counts."""
+        rc = load().graphlet_batch_plan_run(self._h, _stream_ptr(stream))
+        if rc != 0:
+            raise GraphletError(rc, graphlet_last_error())
+        return self.out[:self.G]
+
+    def reshape(self, block: int, class_words, stream=None) -> None:
+        """Forces a workgroup size and the size classes (words per row)."""
+        mask = 0
+        for w in class_words:
+            mask |= 1 << (int(w) - 1)
+        rc = load().graphlet_batch_plan_reshape(self._h, block, mask, _stream_ptr(stream))
+        if rc != 0:
+            raise GraphletError(rc, graphlet_last_error())
+
+    def info(self) -> dict:
+        i = _PlanInfo()
+        rc = load().graphlet_batch_plan_info(self._h, ctypes.byref(i))
+        if rc != 0:
+            raise GraphletError(rc, graphlet_last_error())
+        k = i.classes
+        return {"block": i.block, "classes": k, "class_words": list(i.class_words[:k]),
+                "class_graphs": list(i.class_graphs[:k]), "class_grid": list(i.class_grid[:k]),
+                "class_lds": list(i.class_lds[:k]), "candidates": i.candidates,
+                "tuned_ms": i.tuned_ms}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().graphlet_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def graphlet_timing_enable(on: bool = True) -> None:

@@ -302,3 +302,102 @@ def test_batched_rejects_oversized_graph():
     with pytest.raises(gl.GraphletError) as e:
         batched_gpu(b)
     assert e.value.code == -5
+
+
+# ------------------------------------------------------------ batched plans
+
+CLASS_SETS = [[16], [4, 16], [1, 4, 16], [4, 10, 16], [2, 6, 10, 16], [1, 2, 4, 6, 8, 10, 12, 16]]
+SHAPES = [(blk, cls) for blk in (256, 512) for cls in CLASS_SETS]
+
+
+def mixed_batch_graphs(seed=78):
+    rng = np.random.default_rng(seed)
+    graphs = []
+    for n in [0, 1, 2, 3, 5, 17, 40, 63, 64, 65, 100, 127, 128, 129, 191, 192, 193, 255, 256,
+              257, 300, 400, 640, 641, 1024]:
+        graphs.append(rand_graph(rng, n, float(rng.uniform(0.02, 0.4))))
+    graphs.append(graphgen.rgg_torus(150, 8.0, 5))
+    graphs.append(graphgen.from_edges(70, [(a, b) for a in range(70) for b in range(a + 1, 70)]))
+    return graphs
+
+
+def test_batch_plan_every_shape_vs_oracle():
+    graphs = mixed_batch_graphs()
+    want = [oracle.identity_route(g) for g in graphs]
+    b = make_batch(graphs)
+    with gl.BatchPlan(dev(b.node_off), dev(b.row_ptr), dev(b.col), tune=False) as plan:
+        for blk, cls in SHAPES:
+            plan.reshape(blk, cls)
+            info = plan.info()
+            assert info["block"] == blk and set(info["class_words"]) <= set(cls)
+            assert sum(info["class_graphs"]) == len(graphs)
+            out = plan.run().cpu().numpy()
+            for i, g in enumerate(graphs):
+                assert out[i].tolist() == want[i], (blk, cls, i)
+        with pytest.raises(gl.GraphletError) as e:
+            plan.reshape(256, [4, 10])  # nothing holds the n = 1024 graph
+        assert e.value.code == -1
+
+
+def test_batch_plan_tuned_replays_match_eager():
+    import torch
+
+    b = C.batch8192(512)
+    nd, rp, col = dev(b.node_off), dev(b.row_ptr), dev(b.col)
+    eager = gl.graphlet_count_batched(nd, rp, col).cpu().numpy()
+    with gl.BatchPlan(nd, rp, col, tune=True) as plan:
+        info = plan.info()
+        assert info["candidates"] > 0 and info["tuned_ms"] > 0
+        for rep in range(4):
+            plan.out.zero_()                      # eager work between the replays
+            x = torch.randn(1 << 20, device="cuda:0")
+            (x * x).sum().item()
+            torch.cuda.synchronize()
+            got = plan.run().cpu().numpy()
+            np.testing.assert_array_equal(got, eager, err_msg=f"replay {rep}")
+    rng = np.random.default_rng(5)
+    for i in rng.choice(b.graphs, 40, replace=False):
+        assert eager[i].tolist() == oracle.identity_route(b.graph(int(i))), i
+
+
+def test_batch_plan_new_contents_same_sizes():
+    rng = np.random.default_rng(79)
+    sizes = [30, 90, 250, 500]
+    g1 = [rand_graph(rng, n, 0.2) for n in sizes]
+    b1 = make_batch(g1)
+    nd, rp, col = dev(b1.node_off), dev(b1.row_ptr), dev(b1.col)
+    with gl.BatchPlan(nd, rp, col, tune=False) as plan:
+        assert plan.run().cpu().numpy().tolist() == [oracle.identity_route(g) for g in g1]
+        # relabel every graph: same n and nnz per graph, new adjacency lists
+        g2 = []
+        for g in g1:
+            perm = rng.permutation(g.n)
+            eu, ev = oracle.edges(g)
+            g2.append(graphgen.from_edges(g.n, list(zip(perm[eu], perm[ev]))))
+        b2 = make_batch(g2)
+        assert (b2.node_off == b1.node_off).all() and b2.col.shape == b1.col.shape
+        rp.copy_(dev(b2.row_ptr))
+        col.copy_(dev(b2.col))
+        assert plan.run().cpu().numpy().tolist() == [oracle.identity_route(g) for g in g2]
+
+
+def test_batch_plan_rejects_graph_grown_beyond_its_class():
+    rng = np.random.default_rng(80)
+    small, big = rand_graph(rng, 50, 0.2), rand_graph(rng, 300, 0.1)
+    b1 = make_batch([small, big])
+    b2 = make_batch([big, small])  # same total rows and entries, bins swapped
+    assert b1.row_ptr.shape == b2.row_ptr.shape and b1.col.shape == b2.col.shape
+    nd, rp, col = dev(b1.node_off), dev(b1.row_ptr), dev(b1.col)
+    with gl.BatchPlan(nd, rp, col, tune=False) as plan:
+        plan.reshape(256, [1, 16])
+        plan.run()
+        nd.copy_(dev(b2.node_off))
+        rp.copy_(dev(b2.row_ptr))
+        col.copy_(dev(b2.col))
+        with pytest.raises(gl.GraphletError) as e:
+            plan.run()
+        assert e.value.code == -1
+        plan.reshape(256, [1, 16])  # a new layout for the new contents
+        out = plan.run().cpu().numpy()
+    assert out[0].tolist() == oracle.identity_route(big)
+    assert out[1].tolist() == oracle.identity_route(small)
