@@ -16,6 +16,7 @@ Prints one JSON line (the last line of stdout).  Other workloads:
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -55,12 +56,39 @@ def cpu_baseline(g, seconds: float, seed: int = 0):
                       f"(|Tri_e|, 4-cliques and induced 4-cycles by definition), {dt:.1f} s"}
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_c4_heavy_bal_rmat22_traffic.md")
+TRAFFIC_SOURCES = ["paper_1506_04322_amd/csrc/cycles.hip", "paper_1506_04322_amd/csrc/kernels.h",
+                   "paper_1506_04322_amd/csrc/common.h"]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 byte
+    counters, or None when they were taken on other sources or another
+    workload."""
+    if workload != "rmat22" or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    fields = {}
+    for line in open(TRAFFIC_PROFILE):
+        if ":" in line and not line.startswith(("|", "#", "`")):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("kernel") != kernel:
+        return None
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != fields.get("source_sha256"):
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def roofline_from_timing(t: dict):
     """Dominant counting phase, its algorithmic bytes (4 B per adjacency entry
     the phase must read) over its measured device time."""
     phases = {
         "cyc_heavy": (t["cyc_heavy_ms"], 4 * t["wedges_heavy"],
-                      "k_c4_heavy", "wedges of heavy vertices x 4 B"),
+                      "k_c4_heavy_bal", "wedges of heavy vertices x 4 B"),
         "cyc_light": (t["cyc_light_ms"], 4 * t["wedges_light"],
                       "k_c4_light", "wedges of light vertices x 4 B"),
         "cliques": (t["cliques_ms"], 4 * t["clique_entries"],
@@ -111,6 +139,7 @@ def run_single(args, torch, gl):
     timing = {k: v / args.steps for k, v in phase_sum.items()}
     log("[bench] phases: " + ", ".join(f"{k}={v:.3f}" for k, v in timing.items() if k.endswith("_ms")))
     name, roof = roofline_from_timing(timing)
+    roof["traffic"] = measured_traffic(roof["kernel"], args.workload)
     value = g.m / (ms / 1e3)
     res = {
         "metric": "edges/sec full k<=4 graphlet counts",
@@ -304,10 +333,13 @@ def main():
                     help="batch: graphs timed with one plain launch each")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy a 1 GiB device buffer 3 times (known bytes per dispatch, "
+                         "to scale hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the design for sharding is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path",
+              file=sys.stderr)
         sys.exit(2)
     import torch
 
@@ -317,6 +349,18 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(3)
     gl.load()
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.int32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 3
+        print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30,
+                          "copy_GBps": 2 * (1 << 30) / dt / 1e9}), flush=True)
+        return
     if args.workload == "batch":
         res = run_batch(args, torch, gl)
     elif args.workload == "serve":

@@ -2,7 +2,7 @@
 // reverse-entry positions, per-vertex work estimates and work lists.
 //
 // The paper's implementation orders neighbour lists and edge jobs by degree
-// (Section 5.2, job batches); here the order is the total order
+// (Section 5.1, batches of edge jobs); here the order is the total order
 // x < y iff (deg x, x) < (deg y, y), applied by relabelling every vertex with
 // its rank.  Under it, every vertex has at most sqrt(2m) upper neighbours,
 // which bounds the per-vertex state of the clique pass, and every 4-cycle has
