@@ -89,6 +89,8 @@ def roofline_from_timing(t: dict):
     phases = {
         "cyc_heavy": (t["cyc_heavy_ms"], 4 * t["wedges_heavy"],
                       "k_c4_heavy_bal", "wedges of heavy vertices x 4 B"),
+        "cyc_dense": (t["cyc_dense_ms"], 4 * t["wedges_dense"],
+                      "k_hub_short/k_hub_long", "wedges of the dense hubs x 4 B"),
         "cyc_light": (t["cyc_light_ms"], 4 * t["wedges_light"],
                       "k_c4_light", "wedges of light vertices x 4 B"),
         "cliques": (t["cliques_ms"], 4 * t["clique_entries"],
@@ -158,7 +160,8 @@ def run_single(args, torch, gl):
                    "params": params, "output": "17 x u128 global counts"},
         "roofline": roof,
         "phases_ms": {k: round(v, 3) for k, v in timing.items() if k.endswith("_ms")},
-        "work": {k: timing[k] for k in ("clique_entries", "wedges_light", "wedges_heavy")},
+        "work": {k: timing[k] for k in ("clique_entries", "wedges_light", "wedges_heavy",
+                                         "wedges_dense", "dense_hubs", "heavy_items")},
         "counts": [str(x) for x in counts],
     }
     if not args.no_cpu_baseline:

@@ -56,6 +56,11 @@ extern "C" {
 
 /* Flags. */
 #define GC_VALIDATE 1u /* check the CSR contract on the device first, O(m log Delta) */
+/* Route of the costliest 4-cycle vertices (global counts only; the counts do
+ * not depend on it).  By default a cost model sends hubs to dense slabs when
+ * a slab pass is cheaper than their wedges by work items. */
+#define GC_DENSE_ALL 2u /* up to 8192 costliest heavy vertices in dense slabs */
+#define GC_DENSE_OFF 4u /* no dense slabs */
 
 /*
  * An undirected simple graph in CSR form, in DEVICE memory owned by the
@@ -195,18 +200,22 @@ void graphlet_batch_plan_destroy(gc_batch_plan *plan);
  *   0 prepass   relabelling by degree, re-sorted lists, work lists
  *   1 cliques   Step 1 and Step 2a (triangles, 4-cliques)
  *   2 cyc-light Step 2b for vertices with few wedges
- *   3 cyc-heavy Step 2b for vertices with many wedges
- *   4 per-edge  per-edge 4-cliques and D_e (only with per_edge_out)
- *   5 step3     Step 3 sums and their reduction
+ *   3 cyc-dense Step 2b for the costliest vertices, counted in slabs of hubs
+ *               by passes over all rows (global counts only)
+ *   4 cyc-heavy Step 2b for the other vertices with many wedges
+ *   5 per-edge  per-edge 4-cliques and D_e (only with per_edge_out)
+ *   6 step3     Step 3 sums and their reduction
  * Enabling costs one event record per phase; results are unchanged.
  */
-#define GC_PHASES 6
+#define GC_PHASES 7
 typedef struct gc_timing {
   double ms[GC_PHASES];      /* device time per phase, milliseconds */
   uint64_t clique_entries;   /* upper-list entries scanned by phase 1 */
   uint64_t wedges_light;     /* wedges aggregated by phase 2 */
-  uint64_t wedges_heavy;     /* wedges aggregated by phase 3 */
-  int64_t heavy_items;       /* work items of phase 3 */
+  uint64_t wedges_heavy;     /* wedges aggregated by phase 4 */
+  int64_t heavy_items;       /* work items of phase 4 */
+  uint64_t wedges_dense;     /* wedges of the hubs of phase 3 */
+  int64_t dense_hubs;        /* hubs counted by phase 3 */
 } gc_timing;
 
 void graphlet_timing_enable(int on);

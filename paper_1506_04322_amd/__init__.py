@@ -24,6 +24,8 @@ LIB_PATH = os.path.join(HERE, "libgraphlet.so")
 NAMES = ["g2_1", "g2_2", "g3_1", "g3_2", "g3_3", "g3_4"] + [f"g4_{i}" for i in range(1, 12)]
 
 GC_VALIDATE = 1
+GC_DENSE_ALL = 2
+GC_DENSE_OFF = 4
 ERRORS = {
     -1: "GC_EINVAL", -2: "GC_ENOTSORTED", -3: "GC_ESELFLOOP", -4: "GC_EASYMMETRIC",
     -5: "GC_EOVERFLOW", -6: "GC_ENOMEM", -7: "GC_EHIP", -8: "GC_EINTERNAL",
@@ -95,13 +97,14 @@ class _PlanInfo(ctypes.Structure):
                 ("candidates", ctypes.c_int), ("tuned_ms", ctypes.c_double)]
 
 
-PHASES = ["prepass", "cliques", "cyc_light", "cyc_heavy", "per_edge", "step3"]
+PHASES = ["prepass", "cliques", "cyc_light", "cyc_dense", "cyc_heavy", "per_edge", "step3"]
 
 
 class _Timing(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 6), ("clique_entries", ctypes.c_uint64),
+    _fields_ = [("ms", ctypes.c_double * 7), ("clique_entries", ctypes.c_uint64),
                 ("wedges_light", ctypes.c_uint64), ("wedges_heavy", ctypes.c_uint64),
-                ("heavy_items", ctypes.c_int64)]
+                ("heavy_items", ctypes.c_int64), ("wedges_dense", ctypes.c_uint64),
+                ("dense_hubs", ctypes.c_int64)]
 
 
 def load():
@@ -203,10 +206,11 @@ def graphlet_workspace_size(row_ptr, col, n: int, per_edge: bool = False, stream
 
 
 def graphlet_count(row_ptr, col, n: int, per_edge: bool = False, workspace=None,
-                   validate: bool = False, stream=None, per_edge_out=None):
+                   validate: bool = False, stream=None, per_edge_out=None, dense: str = "auto"):
     """17 exact counts (python ints) of one graph; with per_edge, also a
     device int64 tensor [3, m] (|Tri_e|, 4-cliques, induced 4-cycles per
-    canonical edge)."""
+    canonical edge).  `dense` picks the route of the costliest 4-cycle
+    vertices: "auto" (cost model), "all" (GC_DENSE_ALL) or "off"."""
     import torch
 
     lib = load()
@@ -226,9 +230,10 @@ def graphlet_count(row_ptr, col, n: int, per_edge: bool = False, workspace=None,
         _check_dev(workspace, torch.uint8, "workspace")
         ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel()
     out = (_U128 * 17)()
+    flags = (GC_VALIDATE if validate else 0) | {"auto": 0, "all": GC_DENSE_ALL,
+                                                  "off": GC_DENSE_OFF}[dense]
     rc = lib.graphlet_count(ctypes.byref(g), out, pe.data_ptr() if pe is not None else 0,
-                            ws_ptr, ws_bytes, _stream_ptr(stream),
-                            GC_VALIDATE if validate else 0)
+                            ws_ptr, ws_bytes, _stream_ptr(stream), flags)
     if rc != 0:
         raise GraphletError(rc, graphlet_last_error())
     counts = [int(o.lo) | (int(o.hi) << 64) for o in out]
@@ -340,7 +345,8 @@ def graphlet_last_timing() -> dict:
     load().graphlet_last_timing(ctypes.byref(t))
     d = {f"{p}_ms": float(t.ms[i]) for i, p in enumerate(PHASES)}
     d.update(clique_entries=int(t.clique_entries), wedges_light=int(t.wedges_light),
-             wedges_heavy=int(t.wedges_heavy), heavy_items=int(t.heavy_items))
+             wedges_heavy=int(t.wedges_heavy), heavy_items=int(t.heavy_items),
+             wedges_dense=int(t.wedges_dense), dense_hubs=int(t.dense_hubs))
     return d
 
 

@@ -496,7 +496,178 @@ __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
   if (threadIdx.x == 0 && s) atomic_add_u128(g.c4ni, s);
 }
 
+// ------------------------------------------------------------ dense hub slabs
+
+// Number of the slab's hubs above rank y (xs descending: a prefix).
+__device__ __forceinline__ int hubs_above(const int32_t *xs, int nslab, int y) {
+  int lo = 0, hi = nslab;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (xs[mid] > y) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// First rank whose degree exceeds kDenseShortDeg (degrees grow with rank).
+__device__ int first_long_row(const int32_t *rp2, int64_t n) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (rp2[mid + 1] - rp2[mid] > kDenseShortDeg) hi = mid;
+    else lo = mid + 1;
+  }
+  return (int)lo;
+}
+
+// Sets (or clears) bit k of the mask of every lower neighbour of hub k.
+template <bool SET>
+__global__ void k_hub_mark(HubArgs g) {
+  const int k = blockIdx.x;
+  if (k >= g.nslab) return;
+  const int x = g.xs[k];
+  const int a = g.rp2[x], nl = g.lcnt[x];
+  const u64 bit = 1ull << (k & 63);
+  for (int i = threadIdx.x; i < nl; i += blockDim.x) {
+    const size_t v = (size_t)g.col2[a + i];
+    if (SET) {
+      atomicOr(&g.mask[2 * v + (k >> 6)], bit);
+    } else {
+      g.mask[2 * v] = 0;
+      g.mask[2 * v + 1] = 0;
+    }
+  }
+}
+
+// Adds a one-bit-per-hub mask to 8 bit planes (counters up to 255).
+__device__ __forceinline__ void plane_add(u64 (&P)[8], u64 m) {
+#pragma unroll
+  for (int j = 0; j < 8; j++) {
+    const u64 c = P[j] & m;
+    P[j] ^= m;
+    m = c;
+  }
+}
+
+// sum over the hubs in V of C(c_k, 2), c_k held in 8 bit planes:
+//   sum c^2 - sum c = sum_j (4^j - 2^j) |P_j & V| + 2 sum_{j<j'} 2^(j+j') |P_j & P_j' & V|.
+__device__ __forceinline__ u64 planes_pairs(const u64 (&P)[8], u64 V) {
+  u64 s = 0;
+#pragma unroll
+  for (int j = 1; j < 8; j++) s += (((1ull << (2 * j)) - (1ull << j)) / 2) * __popcll(P[j] & V);
+#pragma unroll
+  for (int j = 0; j < 8; j++)
+#pragma unroll
+    for (int jj = j + 1; jj < 8; jj++) s += (1ull << (j + jj)) * __popcll(P[j] & P[jj] & V);
+  return s;
+}
+
+// Rows y of degree <= kDenseShortDeg below the slab's top hub, one thread
+// each (rows are in degree order, so a wave's rows have similar lengths).
+__global__ __launch_bounds__(256) void k_hub_short(HubArgs g) {
+  __shared__ int32_t xs[kDenseSlab];
+  __shared__ u64 red[32];
+  __shared__ int s_long;
+  for (int k = threadIdx.x; k < g.nslab; k += blockDim.x) xs[k] = g.xs[k];
+  if (threadIdx.x == 0) s_long = first_long_row(g.rp2, g.n);
+  __syncthreads();
+  const int ylim = min(s_long, xs[0]);
+  const ulonglong2 *M = reinterpret_cast<const ulonglong2 *>(g.mask);
+  u64 acc = 0;
+  for (int y = blockIdx.x * blockDim.x + threadIdx.x; y < ylim; y += gridDim.x * blockDim.x) {
+    const int t = hubs_above(xs, g.nslab, y);
+    if (t == 0) continue;
+    u64 P0[8], P1[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) P0[j] = P1[j] = 0;
+    const int a = g.rp2[y], b = g.rp2[y + 1];
+    int p = a;
+    for (; p + 4 <= b; p += 4) {
+      int v[4];
+      ulonglong2 mm[4];
+#pragma unroll
+      for (int r = 0; r < 4; r++) v[r] = g.col2[p + r];
+#pragma unroll
+      for (int r = 0; r < 4; r++) mm[r] = M[v[r]];
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        if (mm[r].x) plane_add(P0, mm[r].x);
+        if (mm[r].y) plane_add(P1, mm[r].y);
+      }
+    }
+    for (; p < b; p++) {
+      const ulonglong2 mm = M[g.col2[p]];
+      if (mm.x) plane_add(P0, mm.x);
+      if (mm.y) plane_add(P1, mm.y);
+    }
+    u64 any = 0;
+#pragma unroll
+    for (int j = 0; j < 8; j++) any |= P0[j] | P1[j];
+    if (!any) continue;
+    const u64 V0 = t >= 64 ? ~0ull : ((1ull << t) - 1);
+    const u64 V1 = t >= 128 ? ~0ull : (t > 64 ? ((1ull << (t - 64)) - 1) : 0ull);
+    acc += planes_pairs(P0, V0) + planes_pairs(P1, V1);
+  }
+  const u128 s = block_sum_u128((u128)acc, red);
+  if (threadIdx.x == 0 && s) atomic_add_u128(g.c4ni, s);
+}
+
+// Rows y of degree > kDenseShortDeg below the slab's top hub, one
+// workgroup each, counters in LDS.
+__global__ __launch_bounds__(256) void k_hub_long(HubArgs g) {
+  __shared__ int32_t xs[kDenseSlab];
+  __shared__ uint32_t cnt[kDenseSlab];
+  __shared__ u64 red[32];
+  __shared__ int s_long;
+  for (int k = threadIdx.x; k < g.nslab; k += blockDim.x) xs[k] = g.xs[k];
+  if (threadIdx.x == 0) s_long = first_long_row(g.rp2, g.n);
+  __syncthreads();
+  const int y0 = s_long, ylim = xs[0];
+  const ulonglong2 *M = reinterpret_cast<const ulonglong2 *>(g.mask);
+  u128 acc = 0;
+  for (int y = y0 + blockIdx.x; y < ylim; y += gridDim.x) {
+    const int t = hubs_above(xs, g.nslab, y);
+    if (t == 0) continue;  // uniform
+    if (threadIdx.x < kDenseSlab) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int a = g.rp2[y], b = g.rp2[y + 1];
+    for (int p = a + threadIdx.x; p < b; p += blockDim.x) {
+      const ulonglong2 mm = M[g.col2[p]];
+      u64 m0 = mm.x, m1 = mm.y;
+      while (m0) {
+        const int k = __builtin_ctzll(m0);
+        m0 &= m0 - 1;
+        if (k < t) atomicAdd(&cnt[k], 1u);
+      }
+      while (m1) {
+        const int k = 64 + __builtin_ctzll(m1);
+        m1 &= m1 - 1;
+        if (k < t) atomicAdd(&cnt[k], 1u);
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < t) acc += (u128)choose2(cnt[threadIdx.x]);
+    __syncthreads();
+  }
+  const u128 s = block_sum_u128(acc, red);
+  if (threadIdx.x == 0 && s) atomic_add_u128(g.c4ni, s);
+}
+
 }  // namespace
+
+int launch_dense_slab(const HubArgs &g, hipStream_t s) {
+  if (g.nslab <= 0) return GC_OK;
+  k_hub_mark<true><<<g.nslab, 256, 0, s>>>(g);
+  GC_TRY_HIP(hipGetLastError());
+  const int cus = 256;
+  k_hub_short<<<cus * 8, 256, 0, s>>>(g);
+  GC_TRY_HIP(hipGetLastError());
+  k_hub_long<<<cus * 4, 256, 0, s>>>(g);
+  GC_TRY_HIP(hipGetLastError());
+  k_hub_mark<false><<<g.nslab, 256, 0, s>>>(g);
+  GC_TRY_HIP(hipGetLastError());
+  return GC_OK;
+}
 
 int launch_cycles_medium(C4Args g, hipStream_t s) {
   if (g.nlist <= 0) return GC_OK;

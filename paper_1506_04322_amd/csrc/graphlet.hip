@@ -14,6 +14,7 @@
 // keep it in global memory, heavy work items).  graphlet_workspace_size
 // bounds both from two cheap device reductions.
 #include <algorithm>
+#include <functional>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -46,6 +47,7 @@ struct Plan {
   int64_t n = 0, nnz = 0, m = 0;
   int B = 1;
   bool per_edge = false;
+  uint32_t flags = 0;
 };
 
 struct Fixed {
@@ -125,6 +127,9 @@ struct Dyn {
   int4 *items;
   u64 *hkeys, *hkeys_alt;
   int64_t *pcount;
+  u64 *hubmask;     // dense hub slabs: 2 mask words per vertex (global mode)
+  int32_t *hubs;    // dense hubs, slab by slab, ranks descending in a slab
+  u64 *hubw;        // wedge counts of the candidate hubs
 };
 
 void alloc_dyn(Arena &a, const Plan &P, const DynNeed &d, Dyn &y) {
@@ -143,6 +148,10 @@ void alloc_dyn(Arena &a, const Plan &P, const DynNeed &d, Dyn &y) {
   y.hkeys = a.take<u64>(nh);
   y.hkeys_alt = a.take<u64>(nh);
   y.pcount = a.take<int64_t>(nh);
+  const bool dense = !P.per_edge && d.nheavy > 0;
+  y.hubmask = dense ? a.take<u64>(2 * (size_t)P.n) : nullptr;
+  y.hubs = dense ? a.take<int32_t>(kDenseHubMax) : nullptr;
+  y.hubw = dense ? a.take<u64>(kDenseHubMax) : nullptr;
   if (a.measuring()) {
     measure_heavy_items(d.nheavy, a);
     if (P.per_edge) {  // scan of the canonical edge offsets
@@ -255,7 +264,7 @@ void counts_no_edges(int64_t n, gc_u128 out[17]) {
 // ------------------------------------------------------------------ timing
 
 struct PhaseEvents {
-  static constexpr int kN = 8;
+  static constexpr int kN = 9;
   hipEvent_t e[kN] = {};
   bool on = false;
   int init(hipStream_t s) {
@@ -400,7 +409,43 @@ int run(const gc_csr *G, gc_u128 out17[17], int64_t *per_edge_out, char *ws, siz
       return GC_ENOMEM;
     }
   }
-  GC_TRY(build_heavy_items(pp, dn.nheavy, dy.items, dy.hkeys, dy.hkeys_alt, dy.pcount, da, s));
+  // Heavy wedge vertices, costliest first; the costliest go to dense hub
+  // slabs while a slab's wedges cost more by the item route than one pass.
+  u64 *hsorted = nullptr;
+  GC_TRY(sort_heavy(pp, dn.nheavy, dy.hkeys, dy.hkeys_alt, &hsorted, da, s));
+  int ndense = 0;
+  u64 dense_wedges = 0;
+  std::vector<int32_t> hubs;
+  const bool dense_all = (P.flags & GC_DENSE_ALL) != 0, dense_off = (P.flags & GC_DENSE_OFF) != 0;
+  if (dy.hubmask) {
+    const int cand = std::min(dn.nheavy, kDenseHubMax);
+    std::vector<int32_t> hx(cand);
+    std::vector<u64> hw(cand);
+    GC_TRY(heavy_top(pp, hsorted, cand, dy.hubs, dy.hubw, s));
+    GC_TRY_HIP(hipMemcpyAsync(hx.data(), dy.hubs, sizeof(int32_t) * cand, hipMemcpyDeviceToHost, s));
+    GC_TRY_HIP(hipMemcpyAsync(hw.data(), dy.hubw, sizeof(u64) * cand, hipMemcpyDeviceToHost, s));
+    GC_TRY_HIP(hipStreamSynchronize(s));
+    for (int b = 0; b < cand; b += kDenseSlab) {
+      const int e = std::min(cand, b + kDenseSlab);
+      u64 w = 0;
+      for (int i = b; i < e; i++) w += hw[i];
+      if (dense_off || (!dense_all && (double)w * kSparseWedgePs < kDenseSlabPs)) break;
+      std::vector<int32_t> slab(hx.begin() + b, hx.begin() + e);
+      std::sort(slab.begin(), slab.end(), std::greater<int32_t>());
+      hubs.insert(hubs.end(), slab.begin(), slab.end());
+      dense_wedges += w;
+      ndense = e;
+    }
+    if (ndense > 0) {
+      GC_TRY_HIP(hipMemcpyAsync(dy.hubs, hubs.data(), sizeof(int32_t) * ndense,
+                                hipMemcpyHostToDevice, s));
+      GC_TRY(fill<u64>(dy.hubmask, 0ull, 2 * n, s));
+    }
+  }
+  GC_TRY(expand_heavy_items(pp, dn.nheavy, ndense, hsorted,
+                            hsorted == dy.hkeys ? dy.hkeys_alt : dy.hkeys, dy.items, dy.pcount, da,
+                            s));
+  if (ndense > 0) GC_TRY_HIP(hipStreamSynchronize(s));  // the host vector goes away later
 
   // -- Steps 1 + 2a
   ev.record(2, s);
@@ -451,6 +496,19 @@ int run(const gc_csr *G, gc_u128 out17[17], int64_t *per_edge_out, char *ws, siz
     GC_TRY(launch_cycles_medium(cm, s));
   }
   ev.record(4, s);
+  for (int b = 0; b < ndense; b += kDenseSlab) {
+    HubArgs hg{};
+    hg.rp2 = pp.rp2;
+    hg.col2 = pp.col2;
+    hg.lcnt = pp.lcnt;
+    hg.n = n;
+    hg.mask = dy.hubmask;
+    hg.xs = dy.hubs + b;
+    hg.nslab = std::min(kDenseSlab, ndense - b);
+    hg.c4ni = &pp.acc->c4ni;
+    GC_TRY(launch_dense_slab(hg, s));
+  }
+  ev.record(5, s);
   if (dn.nheavy > 0) {
     c4.items = dy.items;
     c4.nitems = &pp.acc->nitems;
@@ -463,11 +521,11 @@ int run(const gc_csr *G, gc_u128 out17[17], int64_t *per_edge_out, char *ws, siz
     c4.lmax = std::max(dn.lmax, 1);
     GC_TRY(launch_cycles_heavy(c4, dn.slots, P.per_edge, s));
   }
-  ev.record(5, s);
+  ev.record(6, s);
 
   // -- per-edge 4-cliques and D_e (needs final |Tri|)
   if (P.per_edge) GC_TRY(cliques(true));
-  ev.record(6, s);
+  ev.record(7, s);
 
   // -- Step 3
   S3Args s3{};
@@ -494,7 +552,7 @@ int run(const gc_csr *G, gc_u128 out17[17], int64_t *per_edge_out, char *ws, siz
     s3.out = per_edge_out;
   }
   GC_TRY(launch_step3(s3, f.nstep3, P.per_edge, s));
-  ev.record(7, s);
+  ev.record(8, s);
 
   DevAcc h;
   GC_TRY_HIP(hipMemcpyAsync(&h, pp.acc, sizeof h, hipMemcpyDeviceToHost, s));
@@ -507,10 +565,13 @@ int run(const gc_csr *G, gc_u128 out17[17], int64_t *per_edge_out, char *ws, siz
     t.ms[3] = ev.span(4, 5);
     t.ms[4] = ev.span(5, 6);
     t.ms[5] = ev.span(6, 7);
+    t.ms[6] = ev.span(7, 8);
     t.clique_entries = hc.clique_entries;
     t.wedges_light = hc.wedges_light + hc.wedges_medium;
-    t.wedges_heavy = hc.wedges_heavy;
+    t.wedges_heavy = hc.wedges_heavy - dense_wedges;
     t.heavy_items = h.nitems;
+    t.wedges_dense = dense_wedges;
+    t.dense_hubs = ndense;
   }
   u128 A[kAcc];
   for (int i = 0; i < kAcc; i++) A[i] = ((u128)h.step3[i][1] << 64) | h.step3[i][0];
@@ -643,7 +704,8 @@ int count(const gc_csr *g, gc_u128 out[17], int64_t *per_edge_out, void *ws, siz
     return GC_OK;
   }
   if (flags & GC_VALIDATE) GC_TRY(validate(g, s));
-  const Plan P = plan_of(g, per_edge_out != nullptr);
+  Plan P = plan_of(g, per_edge_out != nullptr);
+  P.flags = flags;
   return run(g, out, per_edge_out, reinterpret_cast<char *>(ws), ws ? ws_bytes : 0, s, P);
 }
 

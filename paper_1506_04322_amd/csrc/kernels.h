@@ -116,8 +116,16 @@ int launch_validate(const int32_t *rp, const int32_t *col, int64_t n, int64_t nn
                     hipStream_t s);
 int run_prepass(PrepassArgs &p, Arena &a, hipStream_t s);
 // Heavy wedge items (x, y_begin, y_end), largest first, built on the device.
-int build_heavy_items(const PrepassArgs &p, int nheavy, int4 *items, u64 *keys, u64 *keys_alt,
-                      int64_t *pcount, Arena &a, hipStream_t s);
+// Heavy wedge vertices sorted costliest first (keys: wedge count descending).
+int sort_heavy(const PrepassArgs &p, int nheavy, u64 *keys, u64 *keys_alt, u64 **sorted,
+               Arena &a, hipStream_t s);
+// Rank and wedge count of the first `cnt` sorted heavy vertices.
+int heavy_top(const PrepassArgs &p, const u64 *sorted, int cnt, int32_t *xs, u64 *ws,
+              hipStream_t s);
+// Work items (x, y range) of the sorted heavy vertices after the first `skip`;
+// `spare` is the other radix buffer (nheavy u64).
+int expand_heavy_items(const PrepassArgs &p, int nheavy, int skip, const u64 *sorted, u64 *spare,
+                       int4 *items, int64_t *pcount, Arena &a, hipStream_t s);
 void measure_heavy_items(int nheavy, Arena &a);
 
 // ---------------------------------------------------------------- cliques
@@ -168,6 +176,25 @@ struct C4Args {
   u64 *gacc;      // per slot (per-edge): credit for edge (x, v)
   int lmax;
 };
+
+// Dense hub slabs (global mode).  The costliest heavy vertices are counted
+// kDenseSlab at a time: every vertex v gets a mask whose bit k says that v is
+// a lower neighbour of hub k, and one pass over all rows y sums, per hub, the
+// mask bits of y's neighbours, which is c(x_k, y).
+constexpr int kDenseSlab = 128;        // hubs per slab: two mask words per vertex
+constexpr int kDenseHubMax = 8192;     // candidates examined by the host
+constexpr int kDenseShortDeg = 255;    // rows up to this degree: one thread, 8 bit planes
+constexpr double kDenseSlabPs = 1.2e9;      // measured cost of one slab pass (R-MAT s22)
+constexpr double kSparseWedgePs = 4.9;      // measured cost of one heavy wedge by work items
+struct HubArgs {
+  const int32_t *rp2, *col2, *lcnt;
+  int64_t n;
+  u64 *mask;          // 2 words per vertex, zero between slabs
+  const int32_t *xs;  // the slab's hubs, ranks descending
+  int nslab;
+  u64 *c4ni;          // total (128-bit)
+};
+int launch_dense_slab(const HubArgs &g, hipStream_t s);
 
 int launch_cycles_light(C4Args g, bool per_edge, hipStream_t s);
 int launch_cycles_medium(C4Args g, hipStream_t s);

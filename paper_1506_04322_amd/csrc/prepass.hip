@@ -263,10 +263,16 @@ __device__ int64_t piece_count(u64 w, int64_t nchunks) {
   return S;
 }
 
-__global__ void k_heavy_pieces(const u64 *sorted, int nh, const int32_t *c4h, const u64 *W,
-                               const int32_t *lcnt, int64_t *pcount) {
+// Pieces per heavy vertex; the first `skip` (the costliest, counted by the
+// dense hub pass instead) get none.
+__global__ void k_heavy_pieces(const u64 *sorted, int nh, int skip, const int32_t *c4h,
+                               const u64 *W, const int32_t *lcnt, int64_t *pcount) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nh) return;
+  if (s < skip) {
+    pcount[s] = 0;
+    return;
+  }
   const int x = c4h[(int)(sorted[s] & 0xffffffffull)];
   const int64_t K = chunk_span(lcnt[x]);
   const int64_t nchunks = ((int64_t)x + K - 1) / K;
@@ -282,6 +288,7 @@ __global__ void k_heavy_expand(const u64 *sorted, int nh, const int32_t *c4h,
   const int64_t K = chunk_span(lcnt[x]);
   const int64_t nchunks = ((int64_t)x + K - 1) / K;
   const int64_t S = pcount[s], base = poff[s];
+  if (s == nh - 1) *nitems = base + S;
   for (int64_t k = 0; k < S; k++) {
     const int64_t hi = nchunks - piece_top(k);
     int64_t lo = k == S - 1 ? 0 : nchunks - piece_top(k + 1);
@@ -290,7 +297,16 @@ __global__ void k_heavy_expand(const u64 *sorted, int nh, const int32_t *c4h,
     const int yb = (int)(hi * K < x ? hi * K : x);
     items[base + k] = make_int4(x, ya, yb, 0);
   }
-  if (s == nh - 1) *nitems = base + S;
+}
+
+// The `cnt` costliest heavy vertices: rank and wedge count.
+__global__ void k_heavy_top(const u64 *sorted, int cnt, const int32_t *c4h, const u64 *W,
+                            int32_t *xs, u64 *ws) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= cnt) return;
+  const int x = c4h[(int)(sorted[s] & 0xffffffffull)];
+  xs[s] = x;
+  ws[s] = W[x];
 }
 
 __global__ void k_max_deg(const int32_t *rp, int64_t n, int32_t *out) {
@@ -393,16 +409,30 @@ void measure_heavy_items(int nheavy, Arena &a) {
   a.release(m0);
 }
 
-int build_heavy_items(const PrepassArgs &p, int nh, int4 *items, u64 *keys, u64 *keys_alt,
-                      int64_t *pcount, Arena &a, hipStream_t s) {
+int sort_heavy(const PrepassArgs &p, int nh, u64 *keys, u64 *keys_alt, u64 **sorted, Arena &a,
+               hipStream_t s) {
+  *sorted = keys;
   if (nh <= 0) return GC_OK;
   k_heavy_keys<<<grid1d(nh, 256), 256, 0, s>>>(p.c4h, nh, p.W, keys);
   GC_TRY_HIP(hipGetLastError());
-  u64 *sorted;
-  GC_TRY(radix_sort_u64(keys, keys_alt, nh, 32 + bits_for((u64)nh), &sorted, a, s));
-  k_heavy_pieces<<<grid1d(nh, 256), 256, 0, s>>>(sorted, nh, p.c4h, p.W, p.lcnt, pcount);
+  GC_TRY(radix_sort_u64(keys, keys_alt, nh, 64, sorted, a, s));  // the key's high half is the order
+  return GC_OK;
+}
+
+int heavy_top(const PrepassArgs &p, const u64 *sorted, int cnt, int32_t *xs, u64 *ws,
+              hipStream_t s) {
+  if (cnt <= 0) return GC_OK;
+  k_heavy_top<<<grid1d(cnt, 256), 256, 0, s>>>(sorted, cnt, p.c4h, p.W, xs, ws);
   GC_TRY_HIP(hipGetLastError());
-  int64_t *poff = reinterpret_cast<int64_t *>(sorted == keys ? keys_alt : keys);
+  return GC_OK;
+}
+
+int expand_heavy_items(const PrepassArgs &p, int nh, int skip, const u64 *sorted, u64 *spare,
+                       int4 *items, int64_t *pcount, Arena &a, hipStream_t s) {
+  if (nh <= 0) return GC_OK;
+  k_heavy_pieces<<<grid1d(nh, 256), 256, 0, s>>>(sorted, nh, skip, p.c4h, p.W, p.lcnt, pcount);
+  GC_TRY_HIP(hipGetLastError());
+  int64_t *poff = reinterpret_cast<int64_t *>(spare);
   GC_TRY(scan_exclusive<int64_t>(pcount, poff, nh, a, s));
   k_heavy_expand<<<grid1d(nh, 256), 256, 0, s>>>(sorted, nh, p.c4h, p.lcnt, poff, pcount, items,
                                                  &p.acc->nitems);

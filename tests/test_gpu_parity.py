@@ -206,6 +206,30 @@ def test_config3_rmat22_full_size():
     assert got[5] > 2**63  # needs the 128-bit path
 
 
+def test_dense_hub_slabs_rmat17():
+    # every route of the costliest 4-cycle vertices gives the oracle's counts
+    g = graphgen.rmat(17, 16, 0.57, 0.19, 0.19, 11)
+    want = oracle.identity_route(g)
+    rp, col = dev(g.row_ptr), dev(g.col)
+    gl.graphlet_timing_enable(True)
+    try:
+        for route in ("all", "off", "auto"):
+            assert gl.graphlet_count(rp, col, g.n, dense=route) == want, route
+            t = gl.graphlet_last_timing()
+            if route == "all":
+                assert t["dense_hubs"] > kDenseSlab and t["wedges_dense"] > 0  # several slabs
+            if route == "off":
+                assert t["dense_hubs"] == 0
+    finally:
+        gl.graphlet_timing_enable(False)
+    # the per-edge run does not use slabs and must agree
+    got2, pe = gpu_counts(g, per_edge=True, validate=False)
+    assert got2 == want
+
+
+kDenseSlab = 128
+
+
 # ------------------------------------------------------------ API behaviour
 
 
