@@ -539,26 +539,28 @@ __global__ void k_hub_mark(HubArgs g) {
   }
 }
 
-// Adds a one-bit-per-hub mask to 8 bit planes (counters up to 255).
-__device__ __forceinline__ void plane_add(u64 (&P)[8], u64 m) {
+// Adds a one-bit-per-hub mask to the bit planes (counters up to 1023).
+constexpr int kShortBits = 10;
+__device__ __forceinline__ void plane_add(u64 (&P)[kShortBits], u64 m) {
 #pragma unroll
-  for (int j = 0; j < 8; j++) {
+  for (int j = 0; j < kShortBits; j++) {
     const u64 c = P[j] & m;
     P[j] ^= m;
     m = c;
   }
 }
 
-// sum over the hubs in V of C(c_k, 2), c_k held in 8 bit planes:
+// sum over the hubs in V of C(c_k, 2), c_k held in bit planes:
 //   sum c^2 - sum c = sum_j (4^j - 2^j) |P_j & V| + 2 sum_{j<j'} 2^(j+j') |P_j & P_j' & V|.
-__device__ __forceinline__ u64 planes_pairs(const u64 (&P)[8], u64 V) {
+__device__ __forceinline__ u64 planes_pairs(const u64 (&P)[kShortBits], u64 V) {
   u64 s = 0;
 #pragma unroll
-  for (int j = 1; j < 8; j++) s += (((1ull << (2 * j)) - (1ull << j)) / 2) * __popcll(P[j] & V);
+  for (int j = 1; j < kShortBits; j++)
+    s += (((1ull << (2 * j)) - (1ull << j)) / 2) * __popcll(P[j] & V);
 #pragma unroll
-  for (int j = 0; j < 8; j++)
+  for (int j = 0; j < kShortBits; j++)
 #pragma unroll
-    for (int jj = j + 1; jj < 8; jj++) s += (1ull << (j + jj)) * __popcll(P[j] & P[jj] & V);
+    for (int jj = j + 1; jj < kShortBits; jj++) s += (1ull << (j + jj)) * __popcll(P[j] & P[jj] & V);
   return s;
 }
 
@@ -577,9 +579,9 @@ __global__ __launch_bounds__(256) void k_hub_short(HubArgs g) {
   for (int y = blockIdx.x * blockDim.x + threadIdx.x; y < ylim; y += gridDim.x * blockDim.x) {
     const int t = hubs_above(xs, g.nslab, y);
     if (t == 0) continue;
-    u64 P0[8], P1[8];
+    u64 P0[kShortBits], P1[kShortBits];
 #pragma unroll
-    for (int j = 0; j < 8; j++) P0[j] = P1[j] = 0;
+    for (int j = 0; j < kShortBits; j++) P0[j] = P1[j] = 0;
     const int a = g.rp2[y], b = g.rp2[y + 1];
     int p = a;
     for (; p + 4 <= b; p += 4) {
@@ -602,7 +604,7 @@ __global__ __launch_bounds__(256) void k_hub_short(HubArgs g) {
     }
     u64 any = 0;
 #pragma unroll
-    for (int j = 0; j < 8; j++) any |= P0[j] | P1[j];
+    for (int j = 0; j < kShortBits; j++) any |= P0[j] | P1[j];
     if (!any) continue;
     const u64 V0 = t >= 64 ? ~0ull : ((1ull << t) - 1);
     const u64 V1 = t >= 128 ? ~0ull : (t > 64 ? ((1ull << (t - 64)) - 1) : 0ull);
@@ -613,10 +615,10 @@ __global__ __launch_bounds__(256) void k_hub_short(HubArgs g) {
 }
 
 // Rows y of degree > kDenseShortDeg below the slab's top hub, one
-// workgroup each, counters in LDS.
+// workgroup each, counters in LDS (a set per wave, added at the end).
 __global__ __launch_bounds__(256) void k_hub_long(HubArgs g) {
   __shared__ int32_t xs[kDenseSlab];
-  __shared__ uint32_t cnt[kDenseSlab];
+  __shared__ uint32_t cnt[256 / kWave][kDenseSlab];  // one set per wave: less contention
   __shared__ u64 red[32];
   __shared__ int s_long;
   for (int k = threadIdx.x; k < g.nslab; k += blockDim.x) xs[k] = g.xs[k];
@@ -628,8 +630,9 @@ __global__ __launch_bounds__(256) void k_hub_long(HubArgs g) {
   for (int y = y0 + blockIdx.x; y < ylim; y += gridDim.x) {
     const int t = hubs_above(xs, g.nslab, y);
     if (t == 0) continue;  // uniform
-    if (threadIdx.x < kDenseSlab) cnt[threadIdx.x] = 0;
+    for (int k = threadIdx.x; k < (256 / kWave) * kDenseSlab; k += blockDim.x) cnt[0][k] = 0;
     __syncthreads();
+    uint32_t *mine = cnt[threadIdx.x / kWave];
     const int a = g.rp2[y], b = g.rp2[y + 1];
     for (int p = a + threadIdx.x; p < b; p += blockDim.x) {
       const ulonglong2 mm = M[g.col2[p]];
@@ -637,16 +640,20 @@ __global__ __launch_bounds__(256) void k_hub_long(HubArgs g) {
       while (m0) {
         const int k = __builtin_ctzll(m0);
         m0 &= m0 - 1;
-        if (k < t) atomicAdd(&cnt[k], 1u);
+        if (k < t) atomicAdd(&mine[k], 1u);
       }
       while (m1) {
         const int k = 64 + __builtin_ctzll(m1);
         m1 &= m1 - 1;
-        if (k < t) atomicAdd(&cnt[k], 1u);
+        if (k < t) atomicAdd(&mine[k], 1u);
       }
     }
     __syncthreads();
-    if (threadIdx.x < t) acc += (u128)choose2(cnt[threadIdx.x]);
+    if (threadIdx.x < t) {
+      u64 c = 0;
+      for (int w = 0; w < 256 / kWave; w++) c += cnt[w][threadIdx.x];
+      acc += (u128)choose2(c);
+    }
     __syncthreads();
   }
   const u128 s = block_sum_u128(acc, red);
