@@ -258,27 +258,24 @@ __device__ void scan_excl(int32_t *A, int k, int32_t *wsum) {
 }
 
 // Medium x (global mode): one workgroup per vertex, c(x, .) in an LDS hash
-// of up to kMediumSlots slots; wedges enumerated flat over batches of lower
-// neighbours so every thread reads a share of each batch.
+// of kMediumSlots slots (keys, and 16-bit counts packed two per word: every
+// count is at most W(x) <= kMediumWedges < 2^16); wedges enumerated flat over
+// batches of lower neighbours so every thread reads a share of each batch.
 __global__ __launch_bounds__(kMediumBlock) void k_c4_medium(C4Args g) {
   __shared__ int32_t hkey[kMediumSlots];
-  __shared__ uint32_t hcnt[kMediumSlots];
+  __shared__ uint32_t hcnt[kMediumSlots / 2];
   __shared__ int32_t sPre[kMediumBlock + 1], sStart[kMediumBlock], sums[kMediumBlock / kWave + 1];
   __shared__ u64 red[32];
   const int tid = threadIdx.x;
-  for (int h = tid; h < kMediumSlots; h += kMediumBlock) {
-    hkey[h] = -1;
-    hcnt[h] = 0;
-  }
+  for (int h = tid; h < kMediumSlots; h += kMediumBlock) hkey[h] = -1;
+  for (int h = tid; h < kMediumSlots / 2; h += kMediumBlock) hcnt[h] = 0;
   __syncthreads();
   u128 acc = 0;
   for (int it = blockIdx.x; it < g.nlist; it += gridDim.x) {
     const int x = g.list[it];
     const u64 w = g.W[x];
-    int hs = 64;
-    while ((u64)hs < 2 * w) hs <<= 1;
-    const uint32_t mask = (uint32_t)hs - 1;
-    const int hbits = __ffs(hs) - 1;
+    // table size: a multiple of 64 above W(x) >= distinct endpoints (load < 3/4)
+    const int hs = (int)min<u64>((u64)kMediumSlots, ((3 * w / 2) + 64) & ~63ull);
     const int Lx = g.rp2[x], nL = g.lcnt[x];
     for (int b = 0; b < nL; b += kMediumBlock) {
       const int nb = min(kMediumBlock, nL - b);
@@ -294,14 +291,14 @@ __global__ __launch_bounds__(kMediumBlock) void k_c4_medium(C4Args g) {
       for (int t = tid; t < total; t += kMediumBlock) {
         const int o = upper_index_dev<int32_t>(sPre, nb, t);
         const int y = g.col2[sStart[o] + (t - sPre[o])];
-        uint32_t h = ((uint32_t)y * 2654435761u) >> (32 - hbits);
+        int h = (int)(((u64)((uint32_t)y * 2654435761u) * (u64)hs) >> 32);
         while (true) {
           const int old = atomicCAS(&hkey[h], -1, y);
           if (old == -1 || old == y) {
-            atomicAdd(&hcnt[h], 1u);
+            atomicAdd(&hcnt[h >> 1], (h & 1) ? 65536u : 1u);
             break;
           }
-          h = (h + 1) & mask;
+          h = h + 1 == hs ? 0 : h + 1;
         }
       }
       __syncthreads();
@@ -309,11 +306,13 @@ __global__ __launch_bounds__(kMediumBlock) void k_c4_medium(C4Args g) {
     u64 part = 0;
     for (int h = tid; h < hs; h += kMediumBlock) {
       if (hkey[h] != -1) {
-        part += choose2(hcnt[h]);
+        const uint32_t pair = hcnt[h >> 1];
+        part += choose2((h & 1) ? (pair >> 16) : (pair & 0xffffu));
         hkey[h] = -1;
-        hcnt[h] = 0;
       }
     }
+    __syncthreads();
+    for (int h = tid; h < (hs + 1) / 2; h += kMediumBlock) hcnt[h] = 0;
     acc += (u128)part;
     __syncthreads();
   }

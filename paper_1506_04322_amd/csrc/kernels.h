@@ -36,10 +36,10 @@ __host__ __device__ inline int tk_class(int k) {
 // Light wedge vertices: at most this many wedges (LDS hash of <= 2048 slots).
 constexpr u64 kLightWedges = 1024;
 constexpr int kHashSlots = 2048;
-// Medium wedge vertices (global mode only): one workgroup, LDS hash at load
-// factor <= 1/2.
-constexpr u64 kMediumWedges = 8192;
-constexpr int kMediumSlots = 16384;
+// Medium wedge vertices (global mode only): one workgroup, LDS hash of
+// kMediumSlots slots (int32 key, 16-bit count) at load factor < 3/4.
+constexpr u64 kMediumWedges = 16384;
+constexpr int kMediumSlots = 22528;
 constexpr int kMediumBlock = 1024;
 // A chunk with at most this many wedges is summed and cleared by revisiting
 // its wedges instead of sweeping every counter word.
