@@ -56,6 +56,10 @@ def _load():
         lib.oracle_per_edge.restype = ctypes.c_int
         lib.oracle_bruteforce_edge4.argtypes = [I64, P, P, I64, P, P, P, P]
         lib.oracle_bruteforce_edge4.restype = ctypes.c_int
+        lib.oracle_edge_local.argtypes = [I64, P, P, I64, P, P, P]
+        lib.oracle_edge_local.restype = ctypes.c_int
+        lib.oracle_edge_local_brute.argtypes = [I64, P, P, I64, P, P, P]
+        lib.oracle_edge_local_brute.restype = ctypes.c_int
         lib.oracle_edges.argtypes = [I64, P, P, P, P]
         lib.oracle_edges.restype = I64
         lib.oracle_classify4.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
@@ -110,6 +114,39 @@ def edges(g) -> tuple[np.ndarray, np.ndarray]:
     ev = np.empty(max(m, 1), dtype=np.int32)
     lib.oracle_edges(n, rp.ctypes.data, col.ctypes.data, eu.ctypes.data, ev.ctypes.data)
     return eu[:m], ev[:m]
+
+
+LOCAL_NAMES = ["T", "S", "I", "TT1", "TT0", "TS1", "TS0", "TI1", "SS1", "SuSv1", "SS0",
+               "SuSv0", "SI1", "TI0", "SI0", "II1", "II0"]
+# graphlet (index into the 17-vector) of each local term, and how many edges
+# that graphlet has (each copy is seen from every one of its edges)
+LOCAL_GRAPHLET = [2, 3, 4, 6, 7, 7, 8, 8, 8, 9, 10, 11, 11, 12, 13, 14, 15]
+GRAPHLET_EDGES = {2: 3, 3: 2, 4: 1, 6: 6, 7: 5, 8: 4, 9: 4, 10: 3, 11: 3, 12: 3, 13: 2, 14: 2,
+                  15: 1}
+
+
+def _local(fn, g, eu, ev) -> np.ndarray:
+    n, rp, col = _csr(g)
+    eu = np.ascontiguousarray(eu, dtype=np.int32)
+    ev = np.ascontiguousarray(ev, dtype=np.int32)
+    k = eu.shape[0]
+    out = np.zeros((max(k, 1), 17), dtype=np.int64)
+    if k:
+        rc = fn(n, rp.ctypes.data, col.ctypes.data, k, eu.ctypes.data, ev.ctypes.data,
+                out.ctypes.data)
+        if rc != 0:
+            raise ValueError(f"edge-local oracle failed (code {rc})")
+    return out[:k]
+
+
+def edge_local(g, eu, ev) -> np.ndarray:
+    """[k, 17] per-edge local vectors (LOCAL_NAMES) by vertex types, Section 4.2."""
+    return _local(_load().oracle_edge_local, g, eu, ev)
+
+
+def edge_local_brute(g, eu, ev) -> np.ndarray:
+    """The same vectors by classifying every 3- and 4-subset containing the edge."""
+    return _local(_load().oracle_edge_local_brute, g, eu, ev)
 
 
 def per_edge(g, eu, ev) -> tuple[np.ndarray, np.ndarray, np.ndarray]:

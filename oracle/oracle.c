@@ -31,6 +31,13 @@
  *                          counting (pattern, extra vertex) pairs.  Pinned
  *                          against oracle_bruteforce on random small graphs.
  *
+ *   oracle_edge_local      per edge, the 4-subsets containing it split by
+ *                          graphlet and by the edge's place in it (the
+ *                          N_{a,b,0/1} terms of Section 4.2), by vertex types;
+ *                          oracle_edge_local_brute gets the same vector by
+ *                          classifying every subset (Table 1) and reading
+ *                          the edge's place from degrees.
+ *
  *   oracle_per_edge        the per-edge quantities of the paper written out
  *                          literally for one edge at a time: |Tri_e|
  *                          (Section 3, triangles), the number of 4-cliques
@@ -527,5 +534,158 @@ int oracle_identity_route(int64_t n, const int32_t *rp, const int32_t *col, orc_
   for (int i = 0; i < 17; i++)
     if (g[i] < 0) return -5;
   for (int i = 0; i < 17; i++) put(&out[i], (u128)g[i]);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Per-edge local 4-node vectors (edge orbits).                             */
+/* ------------------------------------------------------------------------ */
+/*
+ * For an edge e = (u, v), every other vertex w has a type relative to e
+ * (Section 4.2): T (adjacent to u and v, w in Tri_e), Su (adjacent to u
+ * only), Sv (adjacent to v only) or I (adjacent to neither).  The 4-subsets
+ * containing e are the pairs {w, r}; their induced graphlet is fixed by the
+ * two types and by whether w and r are adjacent.  The paper writes N_{a,b}
+ * for the number of pairs of types (a, b), and N_{a,b,1} / N_{a,b,0} for
+ * those whose two vertices are / are not adjacent.
+ *
+ * Output per edge, 17 int64 values (the graphlet and e's place in it):
+ *   [0] |Tri_e|          triangle                            (g3_1)
+ *   [1] |Su| + |Sv|      2-star                              (g3_2)
+ *   [2] I_e              3-node-1-edge                       (g3_3)
+ *   [3] N_{T,T,1}        4-clique                            (g4_1)
+ *   [4] N_{T,T,0}        chordal cycle, e the chord          (g4_2)
+ *   [5] N_{T,S,1}        chordal cycle, e on the cycle       (g4_2)
+ *   [6] N_{T,S,0}        tailed triangle, e in the triangle at the tail's vertex (g4_3)
+ *   [7] N_{T,I,1}        tailed triangle, e in the triangle away from the tail  (g4_3)
+ *   [8] N_{S,S,1}        tailed triangle, e the tail         (g4_3)
+ *   [9] N_{Su,Sv,1}      4-cycle                             (g4_4)
+ *  [10] N_{S,S,0}        3-star                              (g4_5)
+ *  [11] N_{Su,Sv,0}      4-path, e in the middle             (g4_6)
+ *  [12] N_{S,I,1}        4-path, e at an end                 (g4_6)
+ *  [13] N_{T,I,0}        4-node-1-triangle                   (g4_7)
+ *  [14] N_{S,I,0}        4-node-2-star                       (g4_8)
+ *  [15] N_{I,I,1}        4-node-2-edge                       (g4_9)
+ *  [16] N_{I,I,0}        4-node-1-edge                       (g4_10)
+ * where S,S pairs two vertices of the same star (Su,Su or Sv,Sv), T,S a T
+ * vertex with a star vertex, and S,I a star vertex with an I vertex.
+ */
+#define ORC_LOCAL 17
+
+enum { TY_T = 0, TY_SU = 1, TY_SV = 2, TY_I = 3, TY_UV = 4 };
+
+/* The types route: unrestricted counts from the type sizes (Section 4.2),
+ * restricted "1" counts by looking at every edge (w, r) of the graph. */
+int oracle_edge_local(int64_t n, const int32_t *rp, const int32_t *col, int64_t cnt,
+                      const int32_t *eu, const int32_t *ev, int64_t *out) {
+  unsigned char *ty = (unsigned char *)malloc(n > 0 ? (size_t)n : 1);
+  if (!ty) return -3;
+  for (int64_t i = 0; i < cnt; i++) {
+    const int64_t u = eu[i], v = ev[i];
+    if (u < 0 || v < 0 || u >= n || v >= n || !adjacent(rp, col, u, v)) {
+      free(ty);
+      return -2;
+    }
+    for (int64_t w = 0; w < n; w++) {
+      const int au = adjacent(rp, col, w, u), av = adjacent(rp, col, w, v);
+      ty[w] = au && av ? TY_T : au ? TY_SU : av ? TY_SV : TY_I;
+    }
+    ty[u] = ty[v] = TY_UV;
+    int64_t sz[4] = {0, 0, 0, 0};
+    for (int64_t w = 0; w < n; w++)
+      if (ty[w] != TY_UV) sz[ty[w]]++;
+    /* adjacent pairs by type pair: one[a][b], a <= b */
+    int64_t one[4][4];
+    memset(one, 0, sizeof one);
+    for (int64_t w = 0; w < n; w++) {
+      if (ty[w] == TY_UV) continue;
+      for (int64_t j = rp[w]; j < rp[w + 1]; j++) {
+        const int64_t r = col[j];
+        if (r <= w || ty[r] == TY_UV) continue;
+        int a = ty[w], b = ty[r];
+        if (a > b) { int t = a; a = b; b = t; }
+        one[a][b]++;
+      }
+    }
+    const int64_t T = sz[TY_T], Su = sz[TY_SU], Sv = sz[TY_SV], I = sz[TY_I];
+    const int64_t nTT = T * (T - 1) / 2, nTS = T * (Su + Sv);
+    const int64_t nSS = Su * (Su - 1) / 2 + Sv * (Sv - 1) / 2, nSuSv = Su * Sv;
+    const int64_t nTI = T * I, nSI = (Su + Sv) * I, nII = I * (I - 1) / 2;
+    const int64_t oTT = one[TY_T][TY_T], oTS = one[TY_T][TY_SU] + one[TY_T][TY_SV];
+    const int64_t oSS = one[TY_SU][TY_SU] + one[TY_SV][TY_SV], oSuSv = one[TY_SU][TY_SV];
+    const int64_t oTI = one[TY_T][TY_I], oSI = one[TY_SU][TY_I] + one[TY_SV][TY_I];
+    const int64_t oII = one[TY_I][TY_I];
+    int64_t *o = out + i * ORC_LOCAL;
+    o[0] = T;
+    o[1] = Su + Sv;
+    o[2] = I;
+    o[3] = oTT;
+    o[4] = nTT - oTT;
+    o[5] = oTS;
+    o[6] = nTS - oTS;
+    o[7] = oTI;
+    o[8] = oSS;
+    o[9] = oSuSv;
+    o[10] = nSS - oSS;
+    o[11] = nSuSv - oSuSv;
+    o[12] = oSI;
+    o[13] = nTI - oTI;
+    o[14] = nSI - oSI;
+    o[15] = oII;
+    o[16] = nII - oII;
+  }
+  free(ty);
+  return 0;
+}
+
+/* The definition route: every 3- and 4-subset containing u and v is
+ * classified by Table 1 (oracle_classify4), and e's place in its graphlet
+ * is read from the degrees of u and v inside the subset. */
+int oracle_edge_local_brute(int64_t n, const int32_t *rp, const int32_t *col, int64_t cnt,
+                            const int32_t *eu, const int32_t *ev, int64_t *out) {
+  for (int64_t i = 0; i < cnt; i++) {
+    const int64_t u = eu[i], v = ev[i];
+    if (u < 0 || v < 0 || u >= n || v >= n || !adjacent(rp, col, u, v)) return -2;
+    int64_t *o = out + i * ORC_LOCAL;
+    memset(o, 0, sizeof(int64_t) * ORC_LOCAL);
+    for (int64_t w = 0; w < n; w++) {
+      if (w == u || w == v) continue;
+      const int e3 = 1 + adjacent(rp, col, u, w) + adjacent(rp, col, v, w);
+      o[3 - e3]++; /* 3 edges: triangle, 2: 2-star, 1: one edge */
+    }
+    for (int64_t w = 0; w < n; w++)
+      for (int64_t r = w + 1; r < n; r++) {
+        if (w == u || w == v || r == u || r == v) continue;
+        const int64_t vs[4] = {u, v, w, r};
+        int deg[4] = {0, 0, 0, 0}, A[4][4];
+        for (int a = 0; a < 4; a++)
+          for (int b = 0; b < 4; b++) {
+            A[a][b] = a != b && adjacent(rp, col, vs[a], vs[b]);
+            deg[a] += A[a][b];
+          }
+        int edges = 0, mx = 0;
+        for (int a = 0; a < 4; a++) {
+          edges += deg[a];
+          mx = deg[a] > mx ? deg[a] : mx;
+        }
+        edges /= 2;
+        const int g = oracle_classify4(edges, mx, components(4, A));
+        const int du = deg[0], dv = deg[1];
+        const int lo = du < dv ? du : dv, hi = du < dv ? dv : du;
+        switch (g) { /* Table 1 row index: 0 = g4_1 ... 9 = g4_10 */
+          case 0: o[3]++; break;                               /* 4-clique */
+          case 1: o[lo == 3 ? 4 : 5]++; break;                 /* chordal cycle */
+          case 2: o[lo == 1 ? 8 : (hi == 3 ? 6 : 7)]++; break; /* tailed triangle */
+          case 3: o[9]++; break;                               /* 4-cycle */
+          case 4: o[10]++; break;                              /* 3-star */
+          case 5: o[lo == 2 ? 11 : 12]++; break;               /* 4-path */
+          case 6: o[13]++; break;                              /* 4-node-1-triangle */
+          case 7: o[14]++; break;                              /* 4-node-2-star */
+          case 8: o[15]++; break;                              /* 4-node-2-edge */
+          case 9: o[16]++; break;                              /* 4-node-1-edge */
+          default: return -4; /* e is an edge: never independent */
+        }
+      }
+  }
   return 0;
 }

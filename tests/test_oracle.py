@@ -383,3 +383,88 @@ def test_wide_counts_exceed_int64():
     c = oracle.identity_route(g)
     assert c[IDX["g3_4"]] == comb(n, 3) and c[IDX["g3_4"]] > 2**63
     assert c[IDX["g4_11"]] == comb(n, 4)
+
+
+# ------------------------------------------------------------ per-edge local vectors
+
+
+def _local_graphs():
+    rng = np.random.default_rng(2024)
+    out = []
+    for _ in range(12):
+        n = int(rng.integers(4, 30))
+        p = float(rng.random())
+        iu = np.triu_indices(n, 1)
+        mask = rng.random(len(iu[0])) < p
+        out.append(graphgen.from_edges(n, list(zip(iu[0][mask], iu[1][mask]))))
+    out.append(graphgen.from_edges(7, [(a, b) for a in range(7) for b in range(a + 1, 7)]))
+    out.append(graphgen.from_edges(9, [(0, i) for i in range(1, 9)]))
+    out.append(graphgen.from_edges(8, [(i, (i + 1) % 8) for i in range(8)]))
+    out.append(graphgen.from_edges(9, [(a, b) for a in range(4) for b in range(4, 9)]))
+    return out
+
+
+@pytest.mark.parametrize("gi", range(16))
+def test_edge_local_two_routes_agree(gi):
+    g = _local_graphs()[gi]
+    eu, ev = oracle.edges(g)
+    if len(eu):
+        np.testing.assert_array_equal(oracle.edge_local(g, eu, ev),
+                                      oracle.edge_local_brute(g, eu, ev))
+
+
+@pytest.mark.parametrize("gi", range(16))
+def test_edge_local_sums(gi):
+    # every 3- and 4-subset containing e is counted once; summed over the
+    # edges, each graphlet is seen once from each of its edges
+    g = _local_graphs()[gi]
+    eu, ev = oracle.edges(g)
+    if not len(eu):
+        return
+    L = oracle.edge_local(g, eu, ev)
+    n = g.n
+    assert (L[:, :3].sum(1) == n - 2).all()
+    assert (L[:, 3:].sum(1) == comb(n - 2, 2)).all()
+    counts = oracle.bruteforce(g)
+    tot = {}
+    for j, G in enumerate(oracle.LOCAL_GRAPHLET):
+        tot[G] = tot.get(G, 0) + int(L[:, j].sum())
+    for G, s in tot.items():
+        assert s == oracle.GRAPHLET_EDGES[G] * counts[G], (G, s, counts[G])
+
+
+def test_edge_local_closed_forms():
+    names = oracle.LOCAL_NAMES
+    # K_n: every other pair of vertices closes a 4-clique
+    n = 8
+    g = graphgen.from_edges(n, [(a, b) for a in range(n) for b in range(a + 1, n)])
+    L = oracle.edge_local(g, [0], [5])[0]
+    want = dict.fromkeys(names, 0)
+    want.update(T=n - 2, TT1=comb(n - 2, 2))
+    assert dict(zip(names, L.tolist())) == want
+    # star with k leaves, edge (centre, leaf): k - 1 star vertices, all pairs 3-stars
+    k = 7
+    g = graphgen.from_edges(k + 1, [(0, i) for i in range(1, k + 1)])
+    L = oracle.edge_local(g, [0], [3])[0]
+    want = dict.fromkeys(names, 0)
+    want.update(S=k - 1, SS0=comb(k - 1, 2))
+    assert dict(zip(names, L.tolist())) == want
+    # cycle C_n, edge (0, 1): one star vertex each side, n - 4 others on a path
+    n = 11
+    g = graphgen.from_edges(n, [(i, (i + 1) % n) for i in range(n)])
+    L = oracle.edge_local(g, [0], [1])[0]
+    want = dict.fromkeys(names, 0)
+    want.update(S=2, I=n - 4, SuSv0=1, SI1=2, SI0=2 * (n - 4) - 2, II1=n - 5,
+                II0=comb(n - 4, 2) - (n - 5))
+    assert dict(zip(names, L.tolist())) == want
+
+
+def test_edge_local_planted_mistake_is_caught():
+    # a dropped term (the tail edge case) breaks the per-graphlet sum rule
+    g = _local_graphs()[3]
+    eu, ev = oracle.edges(g)
+    L = oracle.edge_local(g, eu, ev)
+    L[:, 8] = 0
+    counts = oracle.bruteforce(g)
+    s = int(L[:, 6].sum() + L[:, 7].sum() + L[:, 8].sum())
+    assert counts[8] == 0 or s != 4 * counts[8]
