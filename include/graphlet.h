@@ -90,7 +90,7 @@ typedef struct gc_u128 {
 
 /*
  * Bytes of device workspace graphlet_count needs for this graph (per_edge:
- * whether per_edge_out will be requested).  Reads g->n and g->nnz only on the
+ * 0 global counts only, 1 with per_edge_out, 2 for graphlet_count_local).  Reads g->n and g->nnz only on the
  * host, plus the maximum degree on the device (one small stream-ordered read
  * on `stream`, a hipStream_t).  Returns 0 if the sizes are invalid.
  */
@@ -116,6 +116,36 @@ size_t graphlet_workspace_size(const gc_csr *g, int per_edge, void *stream);
  */
 int graphlet_count(const gc_csr *g, gc_u128 out_counts[17], int64_t *per_edge_out,
                    void *workspace, size_t ws_bytes, void *stream, uint32_t flags);
+
+/*
+ * Per-edge local 4-node vectors ("edge orbits"): for every edge e = (u, v),
+ * the 3- and 4-node subsets containing e split by their graphlet and by the
+ * place of e in it, from the unrestricted and restricted counts N_{a,b} and
+ * N_{a,b,0/1} of Section 4.2 (vertex types T, Su, Sv, I relative to e;
+ * Corollaries of Section 4.3 for the restricted counts).  Also fills
+ * out_counts (HOST, as graphlet_count).
+ *   local_out  DEVICE int64[GC_LOCAL * m], component-major: entry
+ *              [j * m + k] is term j of the edge with canonical id k (as
+ *              per_edge_out), terms j =
+ *     0 |Tri_e| (triangle)            1 |Su|+|Sv| (2-star)     2 I_e (3-node-1-edge)
+ *     3 N_{T,T,1} 4-clique            4 N_{T,T,0} chordal cycle, e the chord
+ *     5 N_{T,S,1} chordal cycle, e on the cycle
+ *     6 N_{T,S,0} tailed triangle, e in the triangle at the tail's vertex
+ *     7 N_{T,I,1} tailed triangle, e in the triangle away from the tail
+ *     8 N_{S,S,1} tailed triangle, e the tail      9 N_{Su,Sv,1} 4-cycle
+ *    10 N_{S,S,0} 3-star             11 N_{Su,Sv,0} 4-path, e in the middle
+ *    12 N_{S,I,1} 4-path, e at an end  13 N_{T,I,0} 4-node-1-triangle
+ *    14 N_{S,I,0} 4-node-2-star      15 N_{I,I,1} 4-node-2-edge
+ *    16 N_{I,I,0} 4-node-1-edge
+ *   (S,S: two vertices of the same star; T,S: a Tri_e vertex and a star
+ *   vertex; S,I: a star vertex and an I vertex.)  Terms 3..16 of an edge add
+ *   up to C(n-2, 2); summed over all edges, the terms of a graphlet give its
+ *   count times its number of edges.
+ *   workspace  as graphlet_count, sized with graphlet_workspace_size(g, 2, .)
+ */
+#define GC_LOCAL 17
+int graphlet_count_local(const gc_csr *g, gc_u128 out_counts[17], int64_t *local_out,
+                         void *workspace, size_t ws_bytes, void *stream, uint32_t flags);
 
 /*
  * Many small graphs in one call (the paper's graph-classification use, many

@@ -59,6 +59,7 @@ _lib = None
 EXPORTS = [
     "graphlet_workspace_size",
     "graphlet_count",
+    "graphlet_count_local",
     "graphlet_count_batched",
     "graphlet_batch_plan_create",
     "graphlet_batch_plan_run",
@@ -121,6 +122,9 @@ def load():
     lib.graphlet_count.argtypes = [ctypes.POINTER(_Csr), ctypes.POINTER(_U128), P, P,
                                    ctypes.c_size_t, P, ctypes.c_uint32]
     lib.graphlet_count.restype = ctypes.c_int
+    lib.graphlet_count_local.argtypes = [ctypes.POINTER(_Csr), ctypes.POINTER(_U128), P, P,
+                                         ctypes.c_size_t, P, ctypes.c_uint32]
+    lib.graphlet_count_local.restype = ctypes.c_int
     lib.graphlet_count_batched.argtypes = [ctypes.POINTER(_Batch), P, P, ctypes.c_uint32]
     lib.graphlet_count_batched.restype = ctypes.c_int
     lib.graphlet_batch_plan_create.argtypes = [ctypes.POINTER(_Batch), P, ctypes.c_int, P,
@@ -196,7 +200,7 @@ def _csr(row_ptr, col, n):
     return _Csr(int(n), int(col.numel()), row_ptr.data_ptr(), col.data_ptr() if col.numel() else 0)
 
 
-def graphlet_workspace_size(row_ptr, col, n: int, per_edge: bool = False, stream=None) -> int:
+def graphlet_workspace_size(row_ptr, col, n: int, per_edge=False, stream=None) -> int:
     lib = load()
     g = _csr(row_ptr, col, n)
     size = lib.graphlet_workspace_size(ctypes.byref(g), int(per_edge), _stream_ptr(stream))
@@ -240,6 +244,39 @@ def graphlet_count(row_ptr, col, n: int, per_edge: bool = False, workspace=None,
     if per_edge:
         return counts, pe[:, :m] if pe.dim() == 2 else pe
     return counts
+
+
+LOCAL = 17
+LOCAL_NAMES = ["T", "S", "I", "TT1", "TT0", "TS1", "TS0", "TI1", "SS1", "SuSv1", "SS0",
+               "SuSv0", "SI1", "TI0", "SI0", "II1", "II0"]
+
+
+def graphlet_count_local(row_ptr, col, n: int, workspace=None, validate: bool = False,
+                         stream=None, out=None):
+    """(17 counts, device int64 tensor [17, m]): the per-edge local 4-node
+    vectors (terms LOCAL_NAMES) in canonical edge order."""
+    import torch
+
+    lib = load()
+    g = _csr(row_ptr, col, n)
+    m = g.nnz // 2
+    if out is None:
+        out = torch.empty((LOCAL, max(m, 1)), dtype=torch.int64, device=row_ptr.device)
+    else:
+        _check_dev(out, torch.int64, "out")
+        if out.numel() < LOCAL * m:
+            raise ValueError("out too small")
+    ws_ptr, ws_bytes = 0, 0
+    if workspace is not None:
+        _check_dev(workspace, torch.uint8, "workspace")
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel()
+    res = (_U128 * 17)()
+    rc = lib.graphlet_count_local(ctypes.byref(g), res, out.data_ptr(), ws_ptr, ws_bytes,
+                                  _stream_ptr(stream), GC_VALIDATE if validate else 0)
+    if rc != 0:
+        raise GraphletError(rc, graphlet_last_error())
+    counts = [int(o.lo) | (int(o.hi) << 64) for o in res]
+    return counts, out.view(-1)[:LOCAL * m].view(LOCAL, m)
 
 
 def graphlet_count_batched(node_off, row_ptr, col, out=None, stream=None, validate=False):

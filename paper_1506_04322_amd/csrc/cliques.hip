@@ -276,6 +276,11 @@ __device__ void tk_vertex(const TkArgs &g, int u, int32_t *U, int32_t *V, int32_
         }
         atomicAdd(&A2[i], (u64)Tu[j] + tij - 2);
         atomicAdd(&A2[j], (u64)Tu[i] + tij - 2);
+        if (g.Bw) {  // local vectors: degrees of the third vertex of the triangle
+          atomicAdd(&g.Bw[pos], (u64)g.deg2[u]);
+          atomicAdd(&g.Bw[base + i], (u64)g.deg2[U[j]]);
+          atomicAdd(&g.Bw[base + j], (u64)g.deg2[U[i]]);
+        }
       }
     }
     __syncthreads();

@@ -47,6 +47,7 @@ struct Plan {
   int64_t n = 0, nnz = 0, m = 0;
   int B = 1;
   bool per_edge = false;
+  bool local = false;  // per-edge local 4-node vectors (implies per_edge)
   uint32_t flags = 0;
 };
 
@@ -54,6 +55,7 @@ struct Fixed {
   PrepassArgs pp;
   uint32_t *T;
   u64 *K4w, *C4w, *Dw;
+  u64 *Bw, *tv, *sv;  // local vectors only
   int64_t *cu;
   u64 *partials;
   int nstep3;
@@ -96,6 +98,13 @@ void alloc_fixed(Arena &a, const Plan &P, Fixed &f) {
   } else {
     f.K4w = f.C4w = f.Dw = nullptr;
     f.cu = nullptr;
+  }
+  if (P.local) {
+    f.Bw = a.take<u64>(nnz);
+    f.tv = a.take<u64>(n);
+    f.sv = a.take<u64>(n);
+  } else {
+    f.Bw = f.tv = f.sv = nullptr;
   }
   // temporaries of the prepass sorts and scans, measured only (the real run
   // takes and releases them inside the sort and scan calls)
@@ -316,8 +325,8 @@ inline char *align256(char *p) {
 
 // ------------------------------------------------------------------ pipeline
 
-int run(const gc_csr *G, gc_u128 out17[17], int64_t *per_edge_out, char *ws, size_t ws_bytes,
-        hipStream_t s, const Plan &P) {
+int run(const gc_csr *G, gc_u128 out17[17], int64_t *per_edge_out, int64_t *local_out, char *ws,
+        size_t ws_bytes, hipStream_t s, const Plan &P) {
   const int64_t n = P.n, nnz = P.nnz, m = P.m;
   Owned owned;
   owned.s = s;
@@ -362,6 +371,11 @@ int run(const gc_csr *G, gc_u128 out17[17], int64_t *per_edge_out, char *ws, siz
     GC_TRY(fill<u64>(f.K4w, 0ull, nnz, s));
     GC_TRY(fill<u64>(f.C4w, 0ull, nnz, s));
     GC_TRY(fill<u64>(f.Dw, 0ull, nnz, s));
+    if (P.local) {
+      GC_TRY(fill<u64>(f.Bw, 0ull, nnz, s));
+      GC_TRY(fill<u64>(f.tv, 0ull, n, s));
+      GC_TRY(fill<u64>(f.sv, 0ull, n, s));
+    }
   }
   PhaseEvents ev;
   GC_TRY(ev.init(s));
@@ -462,6 +476,8 @@ int run(const gc_csr *G, gc_u128 out17[17], int64_t *per_edge_out, char *ws, siz
   tk.gI = dy.gI;
   tk.gA = dy.gA;
   tk.kmax = dn.kmax_global;
+  tk.deg2 = pp.deg2;
+  tk.Bw = nullptr;  // set for the per-edge pass below
   auto cliques = [&](bool per_edge) -> int {
     for (int bin = 0; bin < kTkBins; bin++) {
       tk.list = pp.tk[bin];
@@ -524,7 +540,12 @@ int run(const gc_csr *G, gc_u128 out17[17], int64_t *per_edge_out, char *ws, siz
   ev.record(6, s);
 
   // -- per-edge 4-cliques and D_e (needs final |Tri|)
-  if (P.per_edge) GC_TRY(cliques(true));
+  if (P.per_edge) {
+    tk.Bw = f.Bw;
+    GC_TRY(cliques(true));
+  }
+  if (P.local)
+    GC_TRY(launch_vertex_sums(pp.esorted, pp.col2, f.T, pp.deg2, nnz, P.B, f.tv, f.sv, s));
   ev.record(7, s);
 
   // -- Step 3
@@ -550,6 +571,10 @@ int run(const gc_csr *G, gc_u128 out17[17], int64_t *per_edge_out, char *ws, siz
     s3.col = G->col;
     s3.cu = f.cu;
     s3.out = per_edge_out;
+    s3.local = local_out;
+    s3.Bw = f.Bw;
+    s3.tv = f.tv;
+    s3.sv = f.sv;
   }
   GC_TRY(launch_step3(s3, f.nstep3, P.per_edge, s));
   ev.record(8, s);
@@ -667,7 +692,13 @@ size_t workspace_bound(int64_t n, int64_t nnz, int max_deg, int max_ucnt, bool p
 size_t workspace_size(const gc_csr *g, int per_edge, hipStream_t s, int *rc) {
   *rc = check_args(g);
   if (*rc) return 0;
-  const Plan P = plan_of(g, per_edge != 0);
+  if (per_edge < 0 || per_edge > 2) {
+    *rc = GC_EINVAL;
+    set_error("per_edge must be 0, 1 or 2");
+    return 0;
+  }
+  Plan P = plan_of(g, per_edge != 0);
+  P.local = per_edge == 2;
   if (P.n == 0 || P.nnz == 0) return 256;
   int max_deg = 0, max_ucnt = 0;
   *rc = probe_graph(g, s, &max_deg, &max_ucnt);
@@ -681,8 +712,8 @@ size_t workspace_size(const gc_csr *g, int per_edge, hipStream_t s, int *rc) {
   return a.peak + b.peak + 1024;
 }
 
-int count(const gc_csr *g, gc_u128 out[17], int64_t *per_edge_out, void *ws, size_t ws_bytes,
-          hipStream_t s, uint32_t flags) {
+int count(const gc_csr *g, gc_u128 out[17], int64_t *per_edge_out, int64_t *local_out, void *ws,
+          size_t ws_bytes, hipStream_t s, uint32_t flags) {
   GC_TRY(check_args(g));
   if (!out) {
     set_error("null output");
@@ -704,9 +735,11 @@ int count(const gc_csr *g, gc_u128 out[17], int64_t *per_edge_out, void *ws, siz
     return GC_OK;
   }
   if (flags & GC_VALIDATE) GC_TRY(validate(g, s));
-  Plan P = plan_of(g, per_edge_out != nullptr);
+  Plan P = plan_of(g, per_edge_out != nullptr || local_out != nullptr);
+  P.local = local_out != nullptr;
   P.flags = flags;
-  return run(g, out, per_edge_out, reinterpret_cast<char *>(ws), ws ? ws_bytes : 0, s, P);
+  return run(g, out, per_edge_out, local_out, reinterpret_cast<char *>(ws), ws ? ws_bytes : 0, s,
+             P);
 }
 
 }  // namespace gc
@@ -730,7 +763,24 @@ int graphlet_count(const gc_csr *g, gc_u128 out_counts[17], int64_t *per_edge_ou
                    void *workspace, size_t ws_bytes, void *stream, uint32_t flags) {
   gc::clear_error();
   try {
-    return gc::count(g, out_counts, per_edge_out, workspace, ws_bytes, (hipStream_t)stream, flags);
+    return gc::count(g, out_counts, per_edge_out, nullptr, workspace, ws_bytes,
+                     (hipStream_t)stream, flags);
+  } catch (...) {
+    gc::set_error("unexpected exception");
+    return GC_EINTERNAL;
+  }
+}
+
+int graphlet_count_local(const gc_csr *g, gc_u128 out_counts[17], int64_t *local_out,
+                         void *workspace, size_t ws_bytes, void *stream, uint32_t flags) {
+  gc::clear_error();
+  if (!local_out) {
+    gc::set_error("null local output");
+    return GC_EINVAL;
+  }
+  try {
+    return gc::count(g, out_counts, nullptr, local_out, workspace, ws_bytes, (hipStream_t)stream,
+                     flags);
   } catch (...) {
     gc::set_error("unexpected exception");
     return GC_EINTERNAL;
@@ -747,6 +797,6 @@ int graphlet_last_timing(gc_timing *out) {
   return GC_OK;
 }
 
-const char *graphlet_version(void) { return "graphlet-mi355x 0.2"; }
+const char *graphlet_version(void) { return "graphlet-mi355x 0.3"; }
 
 }  // extern "C"

@@ -139,6 +139,8 @@ struct TkArgs {
   uint32_t *T;  // |Tri| per upper position
   u64 *K4w;     // per-edge pass: 4-cliques per upper position
   u64 *Dw;      // per-edge pass: D_e per upper position
+  u64 *Bw;      // per-edge pass (local vectors): sum of deg(w) over w in Tri_e, or null
+  const int32_t *deg2;  // degree by rank
   u64 *k4;      // global mode: number of 4-cliques (128-bit)
   u64 *k4x3;    // fallback kernel: 3 x 4-cliques (128-bit)
   // global storage of the fallback kernel, per workgroup slot
@@ -216,8 +218,19 @@ struct S3Args {
   const int32_t *rp;
   const int32_t *col;
   const int64_t *cu;
-  int64_t *out;  // [3][m]
+  int64_t *out;  // [3][m], or null
+  // local vectors (or null): sum of deg over Tri_e per upper position, and
+  // per vertex (by rank) twice the triangle count and the sum of neighbour
+  // degrees
+  const u64 *Bw, *tv, *sv;
+  int64_t *local;  // [kLocal][m]
 };
+
+constexpr int kLocal = 17;
+// Per vertex by rank: tv += T_e over incident edges (twice its triangles),
+// sv += deg of every neighbour.
+int launch_vertex_sums(const u64 *ekeys, const int32_t *col2, const uint32_t *T,
+                       const int32_t *deg2, int64_t nnz, int B, u64 *tv, u64 *sv, hipStream_t s);
 
 constexpr int kStep3Grid = 2048;
 int launch_step3(S3Args g, int grid, bool per_edge, hipStream_t s);

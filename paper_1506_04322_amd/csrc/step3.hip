@@ -17,6 +17,55 @@ namespace {
 
 __device__ __forceinline__ u64 choose2(u64 c) { return c * (c - 1) / 2; }
 
+// The per-edge local 4-node vector of e = (x, y) (Section 4.2): the
+// unrestricted counts N_{a,b} from T, Su, Sv, I, and the restricted ones
+// N_{a,b,1} from per-edge and per-vertex sums.  With A_u = sum over w in
+// Tri_e of |Tri_(u,w)|, D = A_u + A_v - 2T, B = sum over Tri_e of deg(w),
+// t_u the triangles at u and s_u the degree sum over N(u):
+//   N_{T,S,1}  = D - 4 K4           (each w in Tri_e sees |Tri_(u,w)| - 1
+//                                     vertices of N(u) - v, 2 K4 of them in Tri_e)
+//   N_{S,S,1}  = t_u + t_v + 2 K4 - D - 2T   (edges inside N(u) by kind)
+//   N_{T,I,1}  = B - 2T - 2K4 - N_{T,S,1}     (degrees of the Tri_e vertices)
+//   N_{S,I,1}  = s_u + s_v - d_u - d_v - 2B - (Su + Sv) - (D - 4K4)
+//                - 2 N_{S,S,1} - 2 C4         (degrees of the star vertices)
+//   N_{I,I,1}  = m - (s_u + s_v - B) + e(X), X = N(u) u N(v) holding
+//                e(X) = 1 + 2T + Su + Sv + K4 + N_{T,S,1} + N_{S,S,1} + C4
+// and N_{a,b,0} = N_{a,b} - N_{a,b,1}.  Output order as the oracle's.
+__device__ __forceinline__ void write_local(const S3Args &g, int64_t id, int64_t p, int32_t x,
+                                            int32_t y, int64_t T, int64_t K4, int64_t C4) {
+  const int64_t n = g.n, m = g.m;
+  const int64_t du = g.deg2[x], dv = g.deg2[y];
+  const int64_t Su = du - 1 - T, Sv = dv - 1 - T, S = Su + Sv, I = n - du - dv + T;
+  const int64_t D = (int64_t)g.Dw[p], B = (int64_t)g.Bw[p];
+  const int64_t tu = (int64_t)(g.tv[x] / 2), tw = (int64_t)(g.tv[y] / 2);
+  const int64_t su = (int64_t)g.sv[x], sw = (int64_t)g.sv[y];
+  const int64_t TS1 = D - 4 * K4;
+  const int64_t SS1 = tu + tw + 2 * K4 - D - 2 * T;
+  const int64_t TI1 = B - 2 * T - 2 * K4 - TS1;
+  const int64_t SI1 = su + sw - du - dv - 2 * B - S - (D - 4 * K4) - 2 * SS1 - 2 * C4;
+  const int64_t eX = 1 + 2 * T + S + K4 + TS1 + SS1 + C4;
+  const int64_t II1 = m - (su + sw - B) + eX;
+  const int64_t v[kLocal] = {T,
+                             S,
+                             I,
+                             K4,
+                             T * (T - 1) / 2 - K4,
+                             TS1,
+                             T * S - TS1,
+                             TI1,
+                             SS1,
+                             C4,
+                             Su * (Su - 1) / 2 + Sv * (Sv - 1) / 2 - SS1,
+                             Su * Sv - C4,
+                             SI1,
+                             T * I - TI1,
+                             S * I - SI1,
+                             II1,
+                             I * (I - 1) / 2 - II1};
+#pragma unroll
+  for (int k = 0; k < kLocal; k++) g.local[(int64_t)k * m + id] = v[k];
+}
+
 template <bool PER_EDGE>
 __global__ __launch_bounds__(256) void k_step3(S3Args g) {
   __shared__ u64 red[32];
@@ -57,9 +106,12 @@ __global__ __launch_bounds__(256) void k_step3(S3Args g) {
       const int split = lower_bound_dev<int32_t>(g.col + r0, r1 - r0, lo);
       const int pos = lower_bound_dev<int32_t>(g.col + r0, r1 - r0, hi);
       const int64_t id = g.cu[lo] + (pos - split);
-      g.out[id] = (int64_t)T;
-      g.out[g.m + id] = (int64_t)k4;
-      g.out[2 * g.m + id] = (int64_t)c4;
+      if (g.out) {
+        g.out[id] = (int64_t)T;
+        g.out[g.m + id] = (int64_t)k4;
+        g.out[2 * g.m + id] = (int64_t)c4;
+      }
+      if (g.local) write_local(g, id, p, x, y, (int64_t)T, (int64_t)k4, (int64_t)c4);
     }
   }
   for (int i = 0; i < kAcc; i++) {
@@ -85,6 +137,18 @@ __global__ void k_step3_final(const u64 *partials, int nblocks, DevAcc *acc) {
   }
 }
 
+__global__ void k_vertex_sums(const u64 *ekeys, const int32_t *col2, const uint32_t *T,
+                              const int32_t *deg2, int64_t nnz, int B, u64 *tv, u64 *sv) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nnz) return;
+  const int32_t x = (int32_t)(ekeys[p] >> B), y = col2[p];
+  atomicAdd(&sv[x], (u64)deg2[y]);
+  if (y > x) {
+    atomicAdd(&tv[x], (u64)T[p]);
+    atomicAdd(&tv[y], (u64)T[p]);
+  }
+}
+
 // Upper-neighbour counts in the caller's ids (canonical edge numbering).
 __global__ void k_orig_upper(const int32_t *rp, const int32_t *col, int64_t n, int64_t *up) {
   const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -100,6 +164,14 @@ int launch_step3(S3Args g, int grid, bool per_edge, hipStream_t s) {
   else k_step3<false><<<grid, 256, 0, s>>>(g);
   GC_TRY_HIP(hipGetLastError());
   k_step3_final<<<kAcc, kWave, 0, s>>>(g.partials, grid, g.acc);
+  GC_TRY_HIP(hipGetLastError());
+  return GC_OK;
+}
+
+int launch_vertex_sums(const u64 *ekeys, const int32_t *col2, const uint32_t *T,
+                       const int32_t *deg2, int64_t nnz, int B, u64 *tv, u64 *sv, hipStream_t s) {
+  if (nnz <= 0) return GC_OK;
+  k_vertex_sums<<<grid1d(nnz, 256), 256, 0, s>>>(ekeys, col2, T, deg2, nnz, B, tv, sv);
   GC_TRY_HIP(hipGetLastError());
   return GC_OK;
 }

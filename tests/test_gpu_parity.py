@@ -230,6 +230,76 @@ def test_dense_hub_slabs_rmat17():
 kDenseSlab = 128
 
 
+# ------------------------------------------------------------ per-edge local vectors
+
+
+def gpu_local(g):
+    counts, L = gl.graphlet_count_local(dev(g.row_ptr), dev(g.col), g.n, validate=True)
+    return counts, L.cpu().numpy().T  # [m, 17]
+
+
+def check_local_sums(g, counts, L):
+    n = g.n
+    if len(L):
+        assert (L[:, :3].sum(1) == n - 2).all()
+        assert (L[:, 3:].sum(1) == comb(n - 2, 2)).all()
+    tot = {}
+    for j, G in enumerate(oracle.LOCAL_GRAPHLET):
+        tot[G] = tot.get(G, 0) + int(L[:, j].sum())
+    for G, s in tot.items():
+        assert s == oracle.GRAPHLET_EDGES[G] * counts[G], G
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_edge_local_small_graphs_vs_oracle(seed):
+    rng = np.random.default_rng(3000 + seed)
+    for _ in range(8):
+        n = int(rng.integers(2, 60))
+        g = rand_graph(rng, n, float(rng.random()))
+        counts, L = gpu_local(g)
+        assert counts == oracle.bruteforce(g)
+        eu, ev = oracle.edges(g)
+        if len(eu):
+            np.testing.assert_array_equal(L, oracle.edge_local(g, eu, ev))
+        check_local_sums(g, counts, L)
+
+
+def test_edge_local_skewed_graphs():
+    for g in (graphgen.rmat(13, 16, 0.57, 0.19, 0.19, 12),
+              graphgen.chung_lu(5000, 2.1, 3.0, 60000, 8),
+              graphgen.from_edges(400, [(0, i) for i in range(1, 400)] +
+                                  [(1, i) for i in range(2, 400)])):
+        counts, L = gpu_local(g)
+        assert counts == oracle.identity_route(g)
+        check_local_sums(g, counts, L)
+        idx, eu, ev = _sampled_edges(g, 300, 31)
+        np.testing.assert_array_equal(L[idx], oracle.edge_local(g, eu, ev))
+        # the per-edge arrays of graphlet_count are the same numbers
+        _, pe = gpu_counts(g, per_edge=True, validate=False)
+        np.testing.assert_array_equal(pe[0], L[:, 0])
+        np.testing.assert_array_equal(pe[1], L[:, 3])
+        np.testing.assert_array_equal(pe[2], L[:, 9])
+
+
+def test_edge_local_chung_lu_full_size():
+    g = C.cl()
+    counts, L = gpu_local(g)
+    gd = golden("cl")
+    assert gd is not None and counts == [int(x) for x in gd["counts"]]
+    n = g.n
+    assert (L[:, :3].sum(1) == n - 2).all()
+    assert (L[:, 3:].sum(1) == comb(n - 2, 2)).all()
+    for G in sorted(set(oracle.LOCAL_GRAPHLET)):
+        cols = [j for j, x in enumerate(oracle.LOCAL_GRAPHLET) if x == G]
+        per_edge = L[:, cols].sum(1)  # each below 2^40
+        tot = sum(int(c.sum()) for c in np.array_split(per_edge, 64))  # exact
+        assert tot == oracle.GRAPHLET_EDGES[G] * counts[G], G
+    idx, eu, ev = _sampled_edges(g, 24, 41)
+    keep = np.concatenate([idx[:20], idx[-20:]])
+    sel = np.isin(idx, keep)
+    np.testing.assert_array_equal(L[idx[sel]], oracle.edge_local(g, eu[sel], ev[sel]))
+
+
 # ------------------------------------------------------------ API behaviour
 
 
