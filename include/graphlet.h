@@ -148,6 +148,26 @@ int graphlet_count_local(const gc_csr *g, gc_u128 out_counts[17], int64_t *local
                          void *workspace, size_t ws_bytes, void *stream, uint32_t flags);
 
 /*
+ * Localized update of the counts of one graph when one edge changes
+ * (Section 6.3: counts updated from the neighbourhood of the changed edge
+ * instead of recomputed).  Only the subsets holding both endpoints change
+ * class; their numbers are the terms of the edge's local 4-node vector (as
+ * graphlet_count_local), computed from the lists of u, v and their
+ * neighbours only: O(sum of deg(w) over w in N(u) u N(v)) work.
+ *   g        DEVICE CSR of the graph BEFORE the change (gc_csr contract)
+ *   u, v     the edge's endpoints, u != v, both in [0, n)
+ *   insert   1: the edge is added (it must be absent from g),
+ *            0: the edge is removed (it must be present in g)
+ *   counts   HOST, in: the 17 counts of g; out: the counts after the change
+ * Returns GC_EINVAL if the endpoints are invalid, the edge's presence does
+ * not match `insert`, or the counts cannot be those of g (a count would turn
+ * negative); counts are left unchanged on error.  The caller updates its CSR.
+ * Allocates a stream-ordered scratch of 2 bits per vertex.
+ */
+int graphlet_update_edge(const gc_csr *g, int32_t u, int32_t v, int insert, gc_u128 counts[17],
+                         void *stream);
+
+/*
  * Many small graphs in one call (the paper's graph-classification use, many
  * small networks each described by its k = 2, 3, 4 counts, Section 6).
  *   graphs    G >= 0

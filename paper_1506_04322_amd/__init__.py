@@ -60,6 +60,7 @@ EXPORTS = [
     "graphlet_workspace_size",
     "graphlet_count",
     "graphlet_count_local",
+    "graphlet_update_edge",
     "graphlet_count_batched",
     "graphlet_batch_plan_create",
     "graphlet_batch_plan_run",
@@ -125,6 +126,9 @@ def load():
     lib.graphlet_count_local.argtypes = [ctypes.POINTER(_Csr), ctypes.POINTER(_U128), P, P,
                                          ctypes.c_size_t, P, ctypes.c_uint32]
     lib.graphlet_count_local.restype = ctypes.c_int
+    lib.graphlet_update_edge.argtypes = [ctypes.POINTER(_Csr), ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int, ctypes.POINTER(_U128), P]
+    lib.graphlet_update_edge.restype = ctypes.c_int
     lib.graphlet_count_batched.argtypes = [ctypes.POINTER(_Batch), P, P, ctypes.c_uint32]
     lib.graphlet_count_batched.restype = ctypes.c_int
     lib.graphlet_batch_plan_create.argtypes = [ctypes.POINTER(_Batch), P, ctypes.c_int, P,
@@ -277,6 +281,23 @@ def graphlet_count_local(row_ptr, col, n: int, workspace=None, validate: bool = 
         raise GraphletError(rc, graphlet_last_error())
     counts = [int(o.lo) | (int(o.hi) << 64) for o in res]
     return counts, out.view(-1)[:LOCAL * m].view(LOCAL, m)
+
+
+def graphlet_update_edge(row_ptr, col, n: int, u: int, v: int, insert: bool, counts,
+                         stream=None) -> list:
+    """The 17 counts after inserting (or removing) the edge (u, v) of the
+    graph given by (row_ptr, col), whose counts are `counts`."""
+    lib = load()
+    g = _csr(row_ptr, col, n)
+    arr = (_U128 * 17)()
+    for i, c in enumerate(counts):
+        arr[i].lo = int(c) & ((1 << 64) - 1)
+        arr[i].hi = int(c) >> 64
+    rc = lib.graphlet_update_edge(ctypes.byref(g), int(u), int(v), 1 if insert else 0, arr,
+                                  _stream_ptr(stream))
+    if rc != 0:
+        raise GraphletError(rc, graphlet_last_error())
+    return [int(o.lo) | (int(o.hi) << 64) for o in arr]
 
 
 def graphlet_count_batched(node_off, row_ptr, col, out=None, stream=None, validate=False):

@@ -300,6 +300,58 @@ def test_edge_local_chung_lu_full_size():
     np.testing.assert_array_equal(L[idx[sel]], oracle.edge_local(g, eu[sel], ev[sel]))
 
 
+# ------------------------------------------------------------ edge updates
+
+
+def _toggle(g, a, b):
+    eu, ev = oracle.edges(g)
+    edges = set(zip(eu.tolist(), ev.tolist()))
+    key = (min(a, b), max(a, b))
+    present = key in edges
+    (edges.discard if present else edges.add)(key)
+    return graphgen.from_edges(g.n, sorted(edges)), not present
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_edge_update_chains_vs_recount(seed):
+    rng = np.random.default_rng(5000 + seed)
+    n = int(rng.integers(8, 50))
+    g = rand_graph(rng, n, float(rng.uniform(0.05, 0.6)))
+    counts = oracle.bruteforce(g)
+    for step in range(25):
+        a, b = map(int, rng.choice(n, 2, replace=False))
+        g2, inserted = _toggle(g, a, b)
+        counts = gl.graphlet_update_edge(dev(g.row_ptr), dev(g.col), g.n, a, b, inserted, counts)
+        g = g2
+        assert counts == oracle.bruteforce(g), step
+
+
+def test_edge_update_hub_edges():
+    g = graphgen.rmat(13, 16, 0.57, 0.19, 0.19, 12)
+    counts = gpu_counts(g, validate=False)
+    d = g.degrees()
+    hubs = np.argsort(-d)[:6].tolist()
+    eu, ev = oracle.edges(g)
+    pairs = [(hubs[0], int(g.col[g.row_ptr[hubs[0]]]))]  # an edge at the top hub
+    pairs += [(hubs[i], hubs[j]) for i in range(3) for j in range(i + 1, 6)][:4]
+    for a, b in pairs:
+        g2, inserted = _toggle(g, a, b)
+        counts = gl.graphlet_update_edge(dev(g.row_ptr), dev(g.col), g.n, a, b, inserted, counts)
+        g = g2
+        assert counts == gpu_counts(g, validate=False)
+    assert counts == oracle.identity_route(g)
+
+
+def test_edge_update_rejects_bad_requests():
+    g = graphgen.from_edges(6, [(0, 1), (1, 2), (2, 3)])
+    c = oracle.bruteforce(g)
+    rp, col = dev(g.row_ptr), dev(g.col)
+    for a, b, ins in [(0, 1, True), (0, 2, False), (3, 3, True), (0, 9, True)]:
+        with pytest.raises(gl.GraphletError) as e:
+            gl.graphlet_update_edge(rp, col, g.n, a, b, ins, c)
+        assert e.value.code == -1
+
+
 # ------------------------------------------------------------ API behaviour
 
 
