@@ -12,6 +12,8 @@ Prints one JSON line (the last line of stdout).  Other workloads:
                            plain call per graph
   --workload serve         Poisson request stream through the serving loop,
                            against plain per-request launches
+  --workload update        single-edge deletions and insertions on R-MAT
+                           scale 22 by localized update, against a recount
 """
 from __future__ import annotations
 
@@ -314,13 +316,72 @@ def run_serve(args, torch, gl):
     }
 
 
+def run_update(args, torch, gl):
+    """Localized edge updates on R-MAT scale 22: each of `--requests` random
+    edges (half of them at the 64 highest-degree vertices) is deleted and
+    inserted again with graphlet_update_edge; the counts must come back to
+    the full count's.  Latency per update against one full recount."""
+    import numpy as np
+
+    import graphgen.configs as C
+
+    g = C.rmat22()
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(g.row_ptr).to(dev)
+    col = torch.from_numpy(g.col).to(dev)
+    t0 = time.perf_counter()
+    base = gl.graphlet_count(rp, col, g.n)
+    torch.cuda.synchronize()
+    full_ms = (time.perf_counter() - t0) * 1e3
+    rng = np.random.default_rng(7)
+    deg = np.diff(g.row_ptr)
+    hubs = np.argsort(-deg)[:64]
+    k = max(2, args.requests // 10)
+    lat = []
+    for i in range(k):
+        u = int(hubs[i % 64]) if i % 2 else int(rng.choice(np.nonzero(deg)[0]))
+        v = int(g.col[g.row_ptr[u] + rng.integers(deg[u])])
+        # the graph without (u, v), as a CSR on the device
+        keep = np.ones(g.col.shape[0], bool)
+        a, b = g.row_ptr[u], g.row_ptr[v]
+        keep[a + np.searchsorted(g.col[a:g.row_ptr[u + 1]], v)] = False
+        keep[b + np.searchsorted(g.col[b:g.row_ptr[v + 1]], u)] = False
+        rp2 = g.row_ptr.copy()
+        rp2[u + 1:] -= 1
+        rp2[v + 1:] -= 1
+        rp_d, col_d = torch.from_numpy(rp2).to(dev), torch.from_numpy(g.col[keep]).to(dev)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        less = gl.graphlet_update_edge(rp, col, g.n, u, v, False, base)
+        t2 = time.perf_counter()
+        back = gl.graphlet_update_edge(rp_d, col_d, g.n, u, v, True, less)
+        t3 = time.perf_counter()
+        if back != base:
+            raise SystemExit("edge update round trip differs from the full count")
+        lat += [(t2 - t1) * 1e3, (t3 - t2) * 1e3]
+    lat = np.array(lat)
+    log(f"[bench] {len(lat)} updates: p50 {np.percentile(lat, 50):.3f} ms, "
+        f"p99 {np.percentile(lat, 99):.3f} ms; full recount {full_ms:.1f} ms")
+    return {
+        "metric": "edge updates/sec (R-MAT s22, localized recount)",
+        "value": 1e3 / float(lat.mean()), "unit": "updates/s", "n_gpus": 1,
+        "steps": int(len(lat)), "warmup": 0, "ms_per_step": float(lat.mean()),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u128 (exact integer)", "data": "synthetic",
+        "config": {"workload": "update", "graph": "rmat22", "n": g.n, "m": g.m,
+                   "edges": "half uniform, half at the 64 highest-degree vertices"},
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "full_recount_ms": full_ms,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rmat22",
-                    choices=["rmat22", "er", "cl", "batch", "serve"])
+                    choices=["rmat22", "er", "cl", "batch", "serve", "update"])
     ap.add_argument("--requests", type=int, default=1000, help="serve: trace length")
     ap.add_argument("--pool", type=int, default=96, help="serve: distinct graphs")
     ap.add_argument("--per-graph-sample", type=int, default=256,
@@ -359,6 +420,8 @@ def main():
         res = run_batch(args, torch, gl)
     elif args.workload == "serve":
         res = run_serve(args, torch, gl)
+    elif args.workload == "update":
+        res = run_update(args, torch, gl)
     else:
         res = run_single(args, torch, gl)
     print(json.dumps(res), flush=True)

@@ -192,6 +192,20 @@ typedef struct gc_batch {
 int graphlet_count_batched(const gc_batch *b, int64_t *out, void *stream, uint32_t flags);
 
 /*
+ * Graphlet frequency distributions of a batch (the normalised counts used to
+ * compare and classify graphs, Section 6.1): for each graph and each size
+ * k = 2, 3, 4, every count of size k divided by the sum of the counts of
+ * size k (connected_only = 0: all classes of that size, a sum of C(n, k);
+ * 1: the connected classes only, the disconnected entries set to 0).
+ *   counts  DEVICE int64[G][17] as written by graphlet_count_batched
+ *   out     DEVICE double[G][17]; an entry whose size has a zero sum is 0
+ * Every quotient is the correctly rounded double of the exact ratio.
+ * Stream-ordered; returns when out is complete.
+ */
+int graphlet_batch_gfd(const int64_t *counts, int64_t graphs, double *out, int connected_only,
+                       void *stream);
+
+/*
  * Batched execution plan, for a batch counted again and again (the same
  * arrays, possibly with new contents of the same sizes).  Creating a plan
  * checks the batch (GC_VALIDATE as above) and bins the graphs into size

@@ -62,6 +62,7 @@ EXPORTS = [
     "graphlet_count_local",
     "graphlet_update_edge",
     "graphlet_count_batched",
+    "graphlet_batch_gfd",
     "graphlet_batch_plan_create",
     "graphlet_batch_plan_run",
     "graphlet_batch_plan_info",
@@ -129,6 +130,8 @@ def load():
     lib.graphlet_update_edge.argtypes = [ctypes.POINTER(_Csr), ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_int, ctypes.POINTER(_U128), P]
     lib.graphlet_update_edge.restype = ctypes.c_int
+    lib.graphlet_batch_gfd.argtypes = [P, ctypes.c_int64, P, ctypes.c_int, P]
+    lib.graphlet_batch_gfd.restype = ctypes.c_int
     lib.graphlet_count_batched.argtypes = [ctypes.POINTER(_Batch), P, P, ctypes.c_uint32]
     lib.graphlet_count_batched.restype = ctypes.c_int
     lib.graphlet_batch_plan_create.argtypes = [ctypes.POINTER(_Batch), P, ctypes.c_int, P,
@@ -314,6 +317,23 @@ def graphlet_count_batched(node_off, row_ptr, col, out=None, stream=None, valida
     b = _Batch(G, node_off.data_ptr(), row_ptr.data_ptr(), col.data_ptr() if col.numel() else 0)
     rc = lib.graphlet_count_batched(ctypes.byref(b), out.data_ptr(), _stream_ptr(stream),
                                     GC_VALIDATE if validate else 0)
+    if rc != 0:
+        raise GraphletError(rc, graphlet_last_error())
+    return out[:G]
+
+
+def graphlet_batch_gfd(counts, connected_only: bool = False, stream=None):
+    """[G, 17] float64 device tensor: per size k, each count over the sum of
+    the size-k counts (all classes, or the connected ones only)."""
+    import torch
+
+    lib = load()
+    _check_dev(counts, torch.int64, "counts")
+    counts = counts.contiguous()
+    G = counts.shape[0]
+    out = torch.empty((max(G, 1), 17), dtype=torch.float64, device=counts.device)
+    rc = lib.graphlet_batch_gfd(counts.data_ptr(), G, out.data_ptr(), 1 if connected_only else 0,
+                                _stream_ptr(stream))
     if rc != 0:
         raise GraphletError(rc, graphlet_last_error())
     return out[:G]

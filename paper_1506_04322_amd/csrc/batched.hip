@@ -239,6 +239,27 @@ __global__ void k_batch_check(const int64_t *node_off, const int32_t *rp, const 
 }
 
 
+// Graphlet frequency distributions (Section 6.1): per graph and per size k,
+// each count over the sum of the counts of that size (all classes, whose sum
+// is C(n, k), or the connected ones only).  Counts of graphs with n <= 1024
+// are below 2^53, so the operands are exact doubles and the quotient is the
+// correctly rounded one.
+__global__ void k_batch_gfd(const int64_t *counts, int64_t G, double *out, int connected) {
+  const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gi >= G) return;
+  const int64_t *c = counts + gi * 17;
+  double *o = out + gi * 17;
+  // [first, end) of each size and the end of its connected classes
+  const int lo[3] = {0, 2, 6}, hi[3] = {2, 6, 17}, hc[3] = {1, 4, 12};
+  for (int k = 0; k < 3; k++) {
+    const int top = connected ? hc[k] : hi[k];
+    int64_t sum = 0;
+    for (int i = lo[k]; i < top; i++) sum += c[i];
+    for (int i = lo[k]; i < hi[k]; i++)
+      o[i] = (i < top && sum > 0) ? (double)c[i] / (double)sum : 0.0;
+  }
+}
+
 __global__ void k_batch_reset(int32_t *err) {
   if (threadIdx.x == 0) *err = 0;
 }
@@ -746,6 +767,26 @@ int graphlet_batch_plan_reshape(gc_batch_plan *p, int block, uint32_t class_word
 }
 
 void graphlet_batch_plan_destroy(gc_batch_plan *p) { gc::destroy_plan(p); }
+
+int graphlet_batch_gfd(const int64_t *counts, int64_t graphs, double *out, int connected_only,
+                       void *stream) {
+  gc::clear_error();
+  if (graphs < 0 || (graphs > 0 && (!counts || !out))) {
+    gc::set_error("invalid arguments");
+    return GC_EINVAL;
+  }
+  if (graphs == 0) return GC_OK;
+  hipStream_t s = (hipStream_t)stream;
+  gc::k_batch_gfd<<<(unsigned)((graphs + 255) / 256), 256, 0, s>>>(counts, graphs, out,
+                                                                  connected_only ? 1 : 0);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    gc::set_error("gfd: %s", hipGetErrorString(e));
+    return GC_EHIP;
+  }
+  return GC_OK;
+}
 
 int graphlet_count_batched(const gc_batch *b, int64_t *out, void *stream, uint32_t flags) {
   gc::clear_error();

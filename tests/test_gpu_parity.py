@@ -450,6 +450,25 @@ def test_batched_rejects_oversized_graph():
     assert e.value.code == -5
 
 
+def test_batch_gfd_exact():
+    b = C.batch8192(300)
+    counts = gl.graphlet_count_batched(dev(b.node_off), dev(b.row_ptr), dev(b.col))
+    c = counts.cpu().numpy()
+    n = np.diff(b.node_off)
+    for connected in (False, True):
+        got = gl.graphlet_batch_gfd(counts, connected_only=connected).cpu().numpy()
+        want = np.zeros(c.shape)
+        for lo, hi, hc in ((0, 2, 1), (2, 6, 4), (6, 17, 12)):
+            top = hc if connected else hi
+            s = c[:, lo:top].sum(1).astype(np.float64)
+            with np.errstate(invalid="ignore", divide="ignore"):
+                q = c[:, lo:top].astype(np.float64) / s[:, None]
+            want[:, lo:top] = np.where(s[:, None] > 0, q, 0.0)
+        np.testing.assert_array_equal(got, want)
+        if not connected:  # all classes: the size-k sums are C(n, k)
+            np.testing.assert_array_equal(c[:, 6:17].sum(1), n * (n - 1) * (n - 2) * (n - 3) // 24)
+
+
 # ------------------------------------------------------------ batched plans
 
 CLASS_SETS = [[16], [4, 16], [1, 4, 16], [4, 10, 16], [2, 6, 10, 16], [1, 2, 4, 6, 8, 10, 12, 16]]
