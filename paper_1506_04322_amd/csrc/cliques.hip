@@ -341,8 +341,8 @@ int launch_cliques(TkArgs g, int bin, bool per_edge, hipStream_t s) {
     switch (bin) {
       case 0: k_tk_up<64, kTkLim0, 256><<<grid(65536), 64, 0, s>>>(g); break;
       case 1: k_tk_up<256, kTkLim1, 1024><<<grid(16384), 256, 0, s>>>(g); break;
-      case 2: k_tk_up<256, kTkLim2, 2048><<<grid(8192), 256, 0, s>>>(g); break;
-      case 3: k_tk_up<512, kTkLim3, 8192><<<grid(4096), 512, 0, s>>>(g); break;
+      case 2: k_tk_up<512, kTkLim2, 2048><<<grid(8192), 512, 0, s>>>(g); break;
+      case 3: k_tk_up<1024, kTkLim3, 4096><<<grid(4096), 1024, 0, s>>>(g); break;
       default: k_tk_global<256, false><<<grid(kTkGlobalSlots), 256, 0, s>>>(g); break;
     }
   } else {
