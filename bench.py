@@ -14,6 +14,7 @@ Prints one JSON line (the last line of stdout).  Other workloads:
                            against plain per-request launches
   --workload update        single-edge deletions and insertions on R-MAT
                            scale 22 by localized update, against a recount
+  --workload vertex        per-vertex counts (17 per vertex) of R-MAT scale 22
 """
 from __future__ import annotations
 
@@ -375,13 +376,81 @@ def run_update(args, torch, gl):
     }
 
 
+def vertex_roofline(g, ms):
+    """k_vertex_counts: one wave per vertex reads its list (col2 4 B, the
+    twin position 4 B for the lower half), the edge's five per-edge words
+    (|Tri| 4 B, K4 / C4 / D / B 8 B each) and the neighbour's degree, triangle
+    and degree-sum words (4 + 8 + 8 B); per vertex its row bounds, lower
+    count, order, own sums and the 17 x 8 B output."""
+    nnz = 2 * g.m
+    nbytes = nnz * (4 + 4 + 32 + 20) + (nnz // 2) * 4 + g.n * (8 + 4 + 4 + 20 + 136)
+    achieved = nbytes / (ms / 1e3) / 1e9 if ms > 0 else 0.0
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_vertex_counts", "phase_ms": round(ms, 3), "bytes_per_launch": nbytes,
+            "work_unit": "per adjacency entry 60 B + 4 B per lower entry, per vertex 172 B"}
+
+
+def run_vertex(args, torch, gl):
+    """Per-vertex counts (17 per vertex, graphlet_count_vertex) of R-MAT
+    scale 22; vertices/s of the whole call, the per-vertex kernel's own
+    device time, and the sum rule (each k-node class seen k times) checked
+    on the device against the global counts."""
+    import graphgen.configs as C
+
+    g = C.rmat22()
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(g.row_ptr).to(dev)
+    col = torch.from_numpy(g.col).to(dev)
+    ws_bytes = gl.graphlet_workspace_size(rp, col, g.n, per_edge=2)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    out = torch.empty((17, g.n), dtype=torch.uint64, device=dev)
+    log(f"[bench] vertex: workspace {ws_bytes / 2**30:.2f} GiB")
+    gl.graphlet_timing_enable(True)
+    for i in range(args.warmup):
+        counts, V = gl.graphlet_count_vertex(rp, col, g.n, workspace=ws, out=out)
+        log(f"[bench] warmup {i} done")
+    torch.cuda.synchronize()
+    phase_sum = {}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        c, V = gl.graphlet_count_vertex(rp, col, g.n, workspace=ws, out=out)
+        for k, v in gl.graphlet_last_timing().items():
+            phase_sum[k] = phase_sum.get(k, 0) + v
+        if c != counts:
+            raise RuntimeError("counts changed between steps")
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / args.steps * 1e3
+    timing = {k: v / args.steps for k, v in phase_sum.items()}
+    k_of = [2, 2, 3, 3, 3, 3] + [4] * 11
+    Vi = V.view(torch.int64)
+    lo = (Vi & 0xFFFFFFFF).sum(dim=1).tolist()
+    hi = ((Vi >> 32) & 0xFFFFFFFF).sum(dim=1).tolist()
+    for cl in range(17):
+        if lo[cl] + (hi[cl] << 32) != k_of[cl] * counts[cl]:
+            raise SystemExit(f"per-vertex sum rule fails for class {cl}")
+    log(f"[bench] vertex: {ms:.1f} ms per call, kernel {timing['vertex_ms']:.3f} ms")
+    return {
+        "metric": "vertices/sec per-vertex k<=4 graphlet counts (R-MAT s22)",
+        "value": g.n / (ms / 1e3), "unit": "vertices/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64 per vertex, u128 global (exact integer)",
+        "data": "synthetic",
+        "config": {"workload": "vertex", "graph": "rmat22", "n": g.n, "m": g.m,
+                   "csr_sha256": g.sha256(), "output": "17 x u64 per vertex + 17 x u128"},
+        "edges_per_s": g.m / (ms / 1e3),
+        "roofline": vertex_roofline(g, timing["vertex_ms"]),
+        "phases_ms": {k: round(v, 3) for k, v in timing.items() if k.endswith("_ms")},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rmat22",
-                    choices=["rmat22", "er", "cl", "batch", "serve", "update"])
+                    choices=["rmat22", "er", "cl", "batch", "serve", "update", "vertex"])
     ap.add_argument("--requests", type=int, default=1000, help="serve: trace length")
     ap.add_argument("--pool", type=int, default=96, help="serve: distinct graphs")
     ap.add_argument("--per-graph-sample", type=int, default=256,
@@ -422,6 +491,8 @@ def main():
         res = run_serve(args, torch, gl)
     elif args.workload == "update":
         res = run_update(args, torch, gl)
+    elif args.workload == "vertex":
+        res = run_vertex(args, torch, gl)
     else:
         res = run_single(args, torch, gl)
     print(json.dumps(res), flush=True)

@@ -90,7 +90,7 @@ typedef struct gc_u128 {
 
 /*
  * Bytes of device workspace graphlet_count needs for this graph (per_edge:
- * 0 global counts only, 1 with per_edge_out, 2 for graphlet_count_local).  Reads g->n and g->nnz only on the
+ * 0 global counts only, 1 with per_edge_out, 2 for graphlet_count_local and graphlet_count_vertex).  Reads g->n and g->nnz only on the
  * host, plus the maximum degree on the device (one small stream-ordered read
  * on `stream`, a hipStream_t).  Returns 0 if the sizes are invalid.
  */
@@ -146,6 +146,26 @@ int graphlet_count(const gc_csr *g, gc_u128 out_counts[17], int64_t *per_edge_ou
 #define GC_LOCAL 17
 int graphlet_count_local(const gc_csr *g, gc_u128 out_counts[17], int64_t *local_out,
                          void *workspace, size_t ws_bytes, void *stream, uint32_t flags);
+
+/*
+ * Per-vertex graphlet counts: for every vertex v and each of the 17 classes,
+ * the number of k-node subsets S containing v whose induced subgraph is that
+ * class (the node-level counterpart of the edge weights used to rank edges
+ * or nodes by their 4-stars and 4-cliques, subsection "Finding Large Stars,
+ * Cliques, and other Patterns Fast").  Derived from the per-edge local
+ * 4-node vectors of v's edges plus, for the classes in which v can be
+ * isolated, the 2- and 3-node graphlets outside N(v) u {v}.  Summed over v,
+ * the column of a k-node class is k times its global count.  Also fills
+ * out_counts (HOST, as graphlet_count).
+ *   vertex_out  DEVICE uint64[17 * n], class-major: entry [c * n + v] is
+ *               class c (order as out_counts) for the caller's vertex v.
+ *   workspace   as graphlet_count, sized with graphlet_workspace_size(g, 2, .)
+ * Exact in 64 bits while C(n-1, 3) < 2^64 (n up to about 4.8 million);
+ * returns GC_EOVERFLOW for larger n before any work.  vertex_out is complete
+ * when the call returns.
+ */
+int graphlet_count_vertex(const gc_csr *g, gc_u128 out_counts[17], uint64_t *vertex_out,
+                          void *workspace, size_t ws_bytes, void *stream, uint32_t flags);
 
 /*
  * Localized update of the counts of one graph when one edge changes
@@ -269,9 +289,11 @@ void graphlet_batch_plan_destroy(gc_batch_plan *plan);
  *   4 cyc-heavy Step 2b for the other vertices with many wedges
  *   5 per-edge  per-edge 4-cliques and D_e (only with per_edge_out)
  *   6 step3     Step 3 sums and their reduction
+ *   7 vertex    per-vertex counts from the per-edge arrays (only in
+ *               graphlet_count_vertex)
  * Enabling costs one event record per phase; results are unchanged.
  */
-#define GC_PHASES 7
+#define GC_PHASES 8
 typedef struct gc_timing {
   double ms[GC_PHASES];      /* device time per phase, milliseconds */
   uint64_t clique_entries;   /* upper-list entries scanned by phase 1 */

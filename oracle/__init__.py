@@ -10,6 +10,8 @@ Routes (see oracle.c for the definitions each one writes out):
   per_edge(g, edges)   |Tri_e|, 4-cliques and induced 4-cycles through e,
                        literally, one edge at a time
   bruteforce_edge4     4-cliques / 4-cycles through e by subset enumeration
+  vertex_bruteforce    per-vertex counts: every subset credited to its members
+  vertex_by_deletion   per-vertex counts as g(G) - g(G - v) via identity_route
 """
 from __future__ import annotations
 
@@ -56,6 +58,8 @@ def _load():
         lib.oracle_per_edge.restype = ctypes.c_int
         lib.oracle_bruteforce_edge4.argtypes = [I64, P, P, I64, P, P, P, P]
         lib.oracle_bruteforce_edge4.restype = ctypes.c_int
+        lib.oracle_vertex_bruteforce.argtypes = [I64, P, P, P]
+        lib.oracle_vertex_bruteforce.restype = ctypes.c_int
         lib.oracle_edge_local.argtypes = [I64, P, P, I64, P, P, P]
         lib.oracle_edge_local.restype = ctypes.c_int
         lib.oracle_edge_local_brute.argtypes = [I64, P, P, I64, P, P, P]
@@ -114,6 +118,61 @@ def edges(g) -> tuple[np.ndarray, np.ndarray]:
     ev = np.empty(max(m, 1), dtype=np.int32)
     lib.oracle_edges(n, rp.ctypes.data, col.ctypes.data, eu.ctypes.data, ev.ctypes.data)
     return eu[:m], ev[:m]
+
+
+# number of vertices of each of the 17 classes (the order of NAMES)
+CLASS_K = [2, 2, 3, 3, 3, 3] + [4] * 11
+
+
+def vertex_bruteforce(g) -> np.ndarray:
+    """[n, 17] int64: k-subsets containing each vertex, by induced class (definition)."""
+    n, rp, col = _csr(g)
+    out = np.zeros((max(n, 1), 17), dtype=np.int64)
+    rc = _load().oracle_vertex_bruteforce(n, rp.ctypes.data, col.ctypes.data, out.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"per-vertex brute force rejected the graph (code {rc})")
+    return out[:n]
+
+
+def delete_vertex(g, v: int):
+    """G - v: the induced subgraph on V minus {v}, ids above v shifted down by one."""
+    rp = np.asarray(g.row_ptr, dtype=np.int64)
+    col = np.asarray(g.col, dtype=np.int64)
+    n = int(g.n)
+    deg = np.diff(rp)
+    src = np.repeat(np.arange(n, dtype=np.int64), deg)
+    keep = (src != v) & (col != v)
+    src, dst = src[keep], col[keep]
+    src = src - (src > v)
+    dst = dst - (dst > v)
+    cnt = np.bincount(src, minlength=n - 1) if n > 1 else np.zeros(0, dtype=np.int64)
+    rp2 = np.zeros(n, dtype=np.int32)
+    if n > 1:
+        rp2[1:] = np.cumsum(cnt)
+    # rows stay sorted: the shift keeps the order of the remaining ids
+    return _Graph(n - 1, rp2, dst.astype(np.int32))
+
+
+class _Graph:
+    def __init__(self, n, row_ptr, col):
+        self.n, self.row_ptr, self.col = n, row_ptr, col
+
+
+def vertex_by_deletion(g, vertices=None) -> np.ndarray:
+    """[len(vertices), 17] uint64 per-vertex counts as g_c(G) - g_c(G - v).
+
+    A k-subset of class c either contains v or survives in G - v unchanged, so
+    the difference of the two global count vectors (both from
+    identity_route, which knows nothing of vertices) is the per-vertex
+    count.  Exact at any size; costs one identity_route call per vertex."""
+    n = int(g.n)
+    vs = range(n) if vertices is None else [int(v) for v in vertices]
+    full = identity_route(g)
+    rows = []
+    for v in vs:
+        sub = identity_route(delete_vertex(g, v))
+        rows.append([a - b for a, b in zip(full, sub)])
+    return np.array(rows, dtype=np.uint64).reshape(len(rows), 17)
 
 
 LOCAL_NAMES = ["T", "S", "I", "TT1", "TT0", "TS1", "TS0", "TI1", "SS1", "SuSv1", "SS0",

@@ -21,6 +21,9 @@
  *                          components |C|).  Feasible for n up to a few
  *                          hundred.
  *
+ *   oracle_vertex_bruteforce  the same enumeration, crediting each subset to
+ *                          its members: per-vertex counts by definition.
+ *
  *   oracle_identity_route  exact at any size, by a route the paper does not
  *                          use: counts of NON-induced copies of each
  *                          connected pattern (paths, stars, triangles,
@@ -203,6 +206,63 @@ int oracle_bruteforce(int64_t n, const int32_t *rp, const int32_t *col, orc_u128
         }
   free(A);
   for (int i = 0; i < 17; i++) put(&out[i], c[i]);
+  return 0;
+}
+
+/*
+ * Per-vertex counts by the definition: out[v * 17 + c] is the number of
+ * k-subsets S of V with v in S whose induced subgraph is graphlet c (Table 1
+ * classes, output order as above).  Every 2-, 3- and 4-subset is classified
+ * once and credited to each of its members, so summed over v the column of a
+ * k-node class is k times its global count.  Counts fit int64 for the sizes
+ * this enumeration can reach (n <= 2000 here).
+ */
+int oracle_vertex_bruteforce(int64_t n, const int32_t *rp, const int32_t *col, int64_t *out) {
+  if (oracle_check_csr(n, rp, col)) return -1;
+  if (n > 2000) return -2;
+  unsigned char *A = (unsigned char *)calloc((size_t)(n > 0 ? n : 1) * (size_t)(n > 0 ? n : 1), 1);
+  if (!A) return -3;
+  for (int64_t u = 0; u < n; u++)
+    for (int64_t j = rp[u]; j < rp[u + 1]; j++) A[u * n + col[j]] = 1;
+  memset(out, 0, sizeof(int64_t) * 17 * (size_t)n);
+  for (int64_t a = 0; a < n; a++)
+    for (int64_t b = a + 1; b < n; b++) {
+      const int c = A[a * n + b] ? 0 : 1;
+      out[a * 17 + c]++;
+      out[b * 17 + c]++;
+    }
+  for (int64_t a = 0; a < n; a++)
+    for (int64_t b = a + 1; b < n; b++)
+      for (int64_t d = b + 1; d < n; d++) {
+        const int c = 2 + classify3(A[a * n + b] + A[a * n + d] + A[b * n + d]);
+        out[a * 17 + c]++;
+        out[b * 17 + c]++;
+        out[d * 17 + c]++;
+      }
+  for (int64_t a = 0; a < n; a++)
+    for (int64_t b = a + 1; b < n; b++)
+      for (int64_t d = b + 1; d < n; d++)
+        for (int64_t f = d + 1; f < n; f++) {
+          int64_t v[4] = {a, b, d, f};
+          int m4[4][4];
+          int deg[4] = {0, 0, 0, 0}, edges = 0, mx = 0;
+          for (int i = 0; i < 4; i++)
+            for (int j = 0; j < 4; j++) {
+              m4[i][j] = (i != j) && A[v[i] * n + v[j]];
+              deg[i] += m4[i][j];
+            }
+          for (int i = 0; i < 4; i++) {
+            edges += deg[i];
+            mx = deg[i] > mx ? deg[i] : mx;
+          }
+          const int cls = oracle_classify4(edges / 2, mx, components(4, m4));
+          if (cls < 0) {
+            free(A);
+            return -4;
+          }
+          for (int i = 0; i < 4; i++) out[v[i] * 17 + 6 + cls]++;
+        }
+  free(A);
   return 0;
 }
 

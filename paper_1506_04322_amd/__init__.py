@@ -60,6 +60,7 @@ EXPORTS = [
     "graphlet_workspace_size",
     "graphlet_count",
     "graphlet_count_local",
+    "graphlet_count_vertex",
     "graphlet_update_edge",
     "graphlet_count_batched",
     "graphlet_batch_gfd",
@@ -100,11 +101,12 @@ class _PlanInfo(ctypes.Structure):
                 ("candidates", ctypes.c_int), ("tuned_ms", ctypes.c_double)]
 
 
-PHASES = ["prepass", "cliques", "cyc_light", "cyc_dense", "cyc_heavy", "per_edge", "step3"]
+PHASES = ["prepass", "cliques", "cyc_light", "cyc_dense", "cyc_heavy", "per_edge", "step3",
+          "vertex"]
 
 
 class _Timing(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 7), ("clique_entries", ctypes.c_uint64),
+    _fields_ = [("ms", ctypes.c_double * 8), ("clique_entries", ctypes.c_uint64),
                 ("wedges_light", ctypes.c_uint64), ("wedges_heavy", ctypes.c_uint64),
                 ("heavy_items", ctypes.c_int64), ("wedges_dense", ctypes.c_uint64),
                 ("dense_hubs", ctypes.c_int64)]
@@ -127,6 +129,9 @@ def load():
     lib.graphlet_count_local.argtypes = [ctypes.POINTER(_Csr), ctypes.POINTER(_U128), P, P,
                                          ctypes.c_size_t, P, ctypes.c_uint32]
     lib.graphlet_count_local.restype = ctypes.c_int
+    lib.graphlet_count_vertex.argtypes = [ctypes.POINTER(_Csr), ctypes.POINTER(_U128), P, P,
+                                         ctypes.c_size_t, P, ctypes.c_uint32]
+    lib.graphlet_count_vertex.restype = ctypes.c_int
     lib.graphlet_update_edge.argtypes = [ctypes.POINTER(_Csr), ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_int, ctypes.POINTER(_U128), P]
     lib.graphlet_update_edge.restype = ctypes.c_int
@@ -284,6 +289,33 @@ def graphlet_count_local(row_ptr, col, n: int, workspace=None, validate: bool = 
         raise GraphletError(rc, graphlet_last_error())
     counts = [int(o.lo) | (int(o.hi) << 64) for o in res]
     return counts, out.view(-1)[:LOCAL * m].view(LOCAL, m)
+
+
+def graphlet_count_vertex(row_ptr, col, n: int, workspace=None, validate: bool = False,
+                          stream=None, out=None):
+    """(17 counts, device uint64 tensor [17, n]): for each vertex, the number of
+    k-subsets containing it by induced class (order of NAMES)."""
+    import torch
+
+    lib = load()
+    g = _csr(row_ptr, col, n)
+    if out is None:
+        out = torch.empty((17, max(n, 1)), dtype=torch.uint64, device=row_ptr.device)
+    else:
+        _check_dev(out, torch.uint64, "out")
+        if out.numel() < 17 * n:
+            raise ValueError("out too small")
+    ws_ptr, ws_bytes = 0, 0
+    if workspace is not None:
+        _check_dev(workspace, torch.uint8, "workspace")
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel()
+    res = (_U128 * 17)()
+    rc = lib.graphlet_count_vertex(ctypes.byref(g), res, out.data_ptr(), ws_ptr, ws_bytes,
+                                   _stream_ptr(stream), GC_VALIDATE if validate else 0)
+    if rc != 0:
+        raise GraphletError(rc, graphlet_last_error())
+    counts = [int(o.lo) | (int(o.hi) << 64) for o in res]
+    return counts, out.view(-1)[:17 * n].view(17, n)
 
 
 def graphlet_update_edge(row_ptr, col, n: int, u: int, v: int, insert: bool, counts,

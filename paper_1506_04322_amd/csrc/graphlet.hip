@@ -273,7 +273,7 @@ void counts_no_edges(int64_t n, gc_u128 out[17]) {
 // ------------------------------------------------------------------ timing
 
 struct PhaseEvents {
-  static constexpr int kN = 9;
+  static constexpr int kN = 11;  // 0..8 the counting phases, 9..10 per-vertex counts
   hipEvent_t e[kN] = {};
   bool on = false;
   int init(hipStream_t s) {
@@ -325,8 +325,8 @@ inline char *align256(char *p) {
 
 // ------------------------------------------------------------------ pipeline
 
-int run(const gc_csr *G, gc_u128 out17[17], int64_t *per_edge_out, int64_t *local_out, char *ws,
-        size_t ws_bytes, hipStream_t s, const Plan &P) {
+int run(const gc_csr *G, gc_u128 out17[17], int64_t *per_edge_out, int64_t *local_out,
+        u64 *vertex_out, char *ws, size_t ws_bytes, hipStream_t s, const Plan &P) {
   const int64_t n = P.n, nnz = P.nnz, m = P.m;
   Owned owned;
   owned.s = s;
@@ -591,6 +591,7 @@ int run(const gc_csr *G, gc_u128 out17[17], int64_t *per_edge_out, int64_t *loca
     t.ms[4] = ev.span(5, 6);
     t.ms[5] = ev.span(6, 7);
     t.ms[6] = ev.span(7, 8);
+    t.ms[7] = 0.0;
     t.clique_entries = hc.clique_entries;
     t.wedges_light = hc.wedges_light + hc.wedges_medium;
     t.wedges_heavy = hc.wedges_heavy - dense_wedges;
@@ -620,7 +621,34 @@ int run(const gc_csr *G, gc_u128 out17[17], int64_t *per_edge_out, int64_t *loca
     }
     A[A_C4] = (u128)c4;
   }
-  return finalize(A, n, m, out17);
+  GC_TRY(finalize(A, n, m, out17));
+  if (vertex_out) {
+    VxArgs vx{};
+    vx.rp2 = pp.rp2;
+    vx.col2 = pp.col2;
+    vx.lcnt = pp.lcnt;
+    vx.tpos = pp.tpos;
+    vx.deg2 = pp.deg2;
+    vx.order = pp.order;
+    vx.T = f.T;
+    vx.K4w = f.K4w;
+    vx.C4w = f.C4w;
+    vx.Dw = f.Dw;
+    vx.Bw = f.Bw;
+    vx.tv = f.tv;
+    vx.sv = f.sv;
+    vx.n = n;
+    vx.m = m;
+    vx.tri = out17[2].lo;
+    vx.star = out17[3].lo;
+    vx.out = vertex_out;
+    ev.record(9, s);
+    GC_TRY(launch_vertex_counts(vx, s));
+    ev.record(10, s);
+    GC_TRY_HIP(hipStreamSynchronize(s));
+    if (ev.on) t_last_timing.ms[7] = ev.span(9, 10);
+  }
+  return GC_OK;
 }
 
 int check_args(const gc_csr *g) {
@@ -712,12 +740,16 @@ size_t workspace_size(const gc_csr *g, int per_edge, hipStream_t s, int *rc) {
   return a.peak + b.peak + 1024;
 }
 
-int count(const gc_csr *g, gc_u128 out[17], int64_t *per_edge_out, int64_t *local_out, void *ws,
-          size_t ws_bytes, hipStream_t s, uint32_t flags) {
+int count(const gc_csr *g, gc_u128 out[17], int64_t *per_edge_out, int64_t *local_out,
+          u64 *vertex_out, void *ws, size_t ws_bytes, hipStream_t s, uint32_t flags) {
   GC_TRY(check_args(g));
   if (!out) {
     set_error("null output");
     return GC_EINVAL;
+  }
+  if (vertex_out && g->n >= 4 && (choose_h((u128)(g->n - 1), 3) >> 64) != 0) {
+    set_error("per-vertex counts of n = %lld vertices do not fit 64 bits", (long long)g->n);
+    return GC_EOVERFLOW;
   }
   if (g->nnz == 0) {
     if ((flags & GC_VALIDATE) && g->n > 0) {
@@ -732,14 +764,23 @@ int count(const gc_csr *g, gc_u128 out[17], int64_t *per_edge_out, int64_t *loca
         }
     }
     counts_no_edges(g->n, out);
+    if (vertex_out && g->n > 0) {
+      // no edges: every subset containing v is independent
+      const u64 n1 = (u64)g->n - 1;
+      GC_TRY(fill<u64>(vertex_out, 0ull, 17 * g->n, s));
+      GC_TRY(fill<u64>(vertex_out + 1 * g->n, n1, g->n, s));
+      GC_TRY(fill<u64>(vertex_out + 5 * g->n, (u64)choose_h(n1, 2), g->n, s));
+      GC_TRY(fill<u64>(vertex_out + 16 * g->n, (u64)choose_h(n1, 3), g->n, s));
+      GC_TRY_HIP(hipStreamSynchronize(s));
+    }
     return GC_OK;
   }
   if (flags & GC_VALIDATE) GC_TRY(validate(g, s));
-  Plan P = plan_of(g, per_edge_out != nullptr || local_out != nullptr);
-  P.local = local_out != nullptr;
+  Plan P = plan_of(g, per_edge_out != nullptr || local_out != nullptr || vertex_out != nullptr);
+  P.local = local_out != nullptr || vertex_out != nullptr;
   P.flags = flags;
-  return run(g, out, per_edge_out, local_out, reinterpret_cast<char *>(ws), ws ? ws_bytes : 0, s,
-             P);
+  return run(g, out, per_edge_out, local_out, vertex_out, reinterpret_cast<char *>(ws),
+             ws ? ws_bytes : 0, s, P);
 }
 
 }  // namespace gc
@@ -763,7 +804,7 @@ int graphlet_count(const gc_csr *g, gc_u128 out_counts[17], int64_t *per_edge_ou
                    void *workspace, size_t ws_bytes, void *stream, uint32_t flags) {
   gc::clear_error();
   try {
-    return gc::count(g, out_counts, per_edge_out, nullptr, workspace, ws_bytes,
+    return gc::count(g, out_counts, per_edge_out, nullptr, nullptr, workspace, ws_bytes,
                      (hipStream_t)stream, flags);
   } catch (...) {
     gc::set_error("unexpected exception");
@@ -779,8 +820,25 @@ int graphlet_count_local(const gc_csr *g, gc_u128 out_counts[17], int64_t *local
     return GC_EINVAL;
   }
   try {
-    return gc::count(g, out_counts, nullptr, local_out, workspace, ws_bytes, (hipStream_t)stream,
-                     flags);
+    return gc::count(g, out_counts, nullptr, local_out, nullptr, workspace, ws_bytes,
+                     (hipStream_t)stream, flags);
+  } catch (...) {
+    gc::set_error("unexpected exception");
+    return GC_EINTERNAL;
+  }
+}
+
+int graphlet_count_vertex(const gc_csr *g, gc_u128 out_counts[17], uint64_t *vertex_out,
+                          void *workspace, size_t ws_bytes, void *stream, uint32_t flags) {
+  gc::clear_error();
+  if (!vertex_out) {
+    gc::set_error("null per-vertex output");
+    return GC_EINVAL;
+  }
+  try {
+    return gc::count(g, out_counts, nullptr, nullptr, reinterpret_cast<gc::u64 *>(vertex_out),
+                     workspace, ws_bytes,
+                     (hipStream_t)stream, flags);
   } catch (...) {
     gc::set_error("unexpected exception");
     return GC_EINTERNAL;
@@ -797,6 +855,6 @@ int graphlet_last_timing(gc_timing *out) {
   return GC_OK;
 }
 
-const char *graphlet_version(void) { return "graphlet-mi355x 0.3"; }
+const char *graphlet_version(void) { return "graphlet-mi355x 0.4"; }
 
 }  // extern "C"

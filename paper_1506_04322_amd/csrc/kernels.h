@@ -232,6 +232,17 @@ constexpr int kLocal = 17;
 int launch_vertex_sums(const u64 *ekeys, const int32_t *col2, const uint32_t *T,
                        const int32_t *deg2, int64_t nnz, int B, u64 *tv, u64 *sv, hipStream_t s);
 
+// Per-vertex counts from the per-edge arrays of the local-vector pass.
+struct VxArgs {
+  const int32_t *rp2, *col2, *lcnt, *tpos, *deg2, *order;
+  const uint32_t *T;
+  const u64 *K4w, *C4w, *Dw, *Bw, *tv, *sv;
+  int64_t n, m;
+  u64 tri, star;  // global triangles and induced 2-stars, modulo 2^64
+  u64 *out;       // [17][n] by the caller's vertex id
+};
+int launch_vertex_counts(const VxArgs &g, hipStream_t s);
+
 constexpr int kStep3Grid = 2048;
 int launch_step3(S3Args g, int grid, bool per_edge, hipStream_t s);
 int launch_orig_upper(const int32_t *rp, const int32_t *col, int64_t n, int64_t *up,

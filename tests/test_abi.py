@@ -47,6 +47,19 @@ def test_null_arguments_are_rejected_without_touching_a_device():
     bad = gl._Csr(5, 3, 0, 0)  # odd nnz
     assert lib.graphlet_count(ctypes.byref(bad), (gl._U128 * 17)(), None, None, 0, None, 0) == -1
     assert lib.graphlet_count_batched(None, None, None, 0) == -1
+    assert lib.graphlet_count_vertex(None, (gl._U128 * 17)(), None, None, 0, None, 0) == -1
+    assert "null" in gl.graphlet_last_error()
+
+
+def test_vertex_counts_reject_large_n_before_any_device_work():
+    # C(n-1, 3) >= 2^64: refused on the host from n alone (the pointers are
+    # never dereferenced)
+    if not os.path.exists(gl.LIB_PATH):
+        pytest.skip("library not built")
+    lib = gl.load()
+    g = gl._Csr(4_900_000, 0, 0x1000, 0)
+    rc = lib.graphlet_count_vertex(ctypes.byref(g), (gl._U128 * 17)(), 0x1000, None, 0, None, 0)
+    assert rc == -5 and "64 bits" in gl.graphlet_last_error()
 
 
 def test_binding_fails_loudly_when_library_is_missing(tmp_path, monkeypatch):

@@ -300,6 +300,142 @@ def test_edge_local_chung_lu_full_size():
     np.testing.assert_array_equal(L[idx[sel]], oracle.edge_local(g, eu[sel], ev[sel]))
 
 
+# ------------------------------------------------------------ per-vertex counts
+
+
+def gpu_vertex(g, validate=True):
+    counts, V = gl.graphlet_count_vertex(dev(g.row_ptr), dev(g.col), g.n, validate=validate)
+    return counts, V.cpu().numpy().T  # [n, 17] uint64
+
+
+def exact_sum(col):
+    """Exact integer sum of a uint64 column (numpy sums in 32-bit halves)."""
+    col = np.asarray(col, dtype=np.uint64)
+    lo = int((col & np.uint64(0xFFFFFFFF)).sum(dtype=np.uint64))
+    hi = int((col >> np.uint64(32)).sum(dtype=np.uint64))
+    return lo + (hi << 32)
+
+
+def check_vertex_sums(g, counts, V):
+    for c in range(17):
+        assert exact_sum(V[:, c]) == oracle.CLASS_K[c] * counts[c], oracle.NAMES[c]
+    np.testing.assert_array_equal(V[:, 0], g.degrees().astype(np.uint64))
+    n = g.n
+    if n:
+        assert (V[:, :2].sum(1) == n - 1).all()
+        assert (V[:, 2:6].sum(1) == np.uint64(comb(n - 1, 2))).all()
+        assert (V[:, 6:].sum(1) == np.uint64(comb(n - 1, 3))).all()
+
+
+def _sampled_vertices(g, k, seed):
+    rng = np.random.default_rng(seed)
+    d = g.degrees()
+    top = np.argsort(-d, kind="stable")[:10]
+    zero = np.nonzero(d == 0)[0][:3]
+    return np.unique(np.concatenate([rng.integers(0, g.n, k), top, zero, [0, g.n - 1]]))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_vertex_counts_small_graphs_vs_bruteforce(seed):
+    rng = np.random.default_rng(5000 + seed)
+    for _ in range(8):
+        n = int(rng.integers(1, 60))
+        g = rand_graph(rng, n, float(rng.random()))
+        counts, V = gpu_vertex(g)
+        assert counts == oracle.bruteforce(g)
+        np.testing.assert_array_equal(V, oracle.vertex_bruteforce(g).astype(np.uint64))
+
+
+def test_vertex_counts_edge_cases():
+    cases = [graphgen.from_edges(0, []), graphgen.from_edges(1, []),
+             graphgen.from_edges(6, []), graphgen.from_edges(2, [(0, 1)]),
+             graphgen.from_edges(300, [(0, i) for i in range(1, 300)]),
+             graphgen.from_edges(40, [(a, b) for a in range(40) for b in range(a + 1, 40)]),
+             graphgen.from_edges(200, [(2 * i, 2 * i + 1) for i in range(100)])]
+    for g in cases:
+        counts, V = gpu_vertex(g)
+        assert V.shape == (g.n, 17)
+        assert counts == oracle.identity_route(g)
+        if g.n <= 60:
+            np.testing.assert_array_equal(V, oracle.vertex_bruteforce(g).astype(np.uint64))
+        else:
+            vs = _sampled_vertices(g, 20, 7)
+            np.testing.assert_array_equal(V[vs], oracle.vertex_by_deletion(g, vs))
+        check_vertex_sums(g, counts, V)
+
+
+def test_vertex_counts_config1_every_vertex_by_deletion():
+    g = C.er()
+    counts, V = gpu_vertex(g)
+    np.testing.assert_array_equal(V, oracle.vertex_by_deletion(g))
+    check_vertex_sums(g, counts, V)
+
+
+def test_vertex_counts_skewed_graphs_sampled():
+    for g in (graphgen.rmat(12, 16, 0.57, 0.19, 0.19, 5),
+              graphgen.chung_lu(5000, 2.1, 3.0, 60000, 8),
+              graphgen.from_edges(400, [(0, i) for i in range(1, 400)] +
+                                  [(1, i) for i in range(2, 400)])):
+        counts, V = gpu_vertex(g, validate=False)
+        assert counts == oracle.identity_route(g)
+        check_vertex_sums(g, counts, V)
+        vs = _sampled_vertices(g, 60, 17)
+        np.testing.assert_array_equal(V[vs], oracle.vertex_by_deletion(g, vs))
+
+
+def test_vertex_counts_chung_lu_full_size():
+    g = C.cl()
+    counts, V = gpu_vertex(g, validate=False)
+    gd = golden("cl")
+    assert gd is not None and counts == [int(x) for x in gd["counts"]]
+    check_vertex_sums(g, counts, V)
+    # triangles at sampled vertices from the per-edge definition
+    vs = _sampled_vertices(g, 200, 23)
+    eu, ev = oracle.edges(g)
+    for v in vs[:40]:
+        sel = (eu == v) | (ev == v)
+        if sel.any():
+            T, _, _ = oracle.per_edge(g, eu[sel], ev[sel])
+            assert int(V[v, 2]) == int(T.sum()) // 2
+
+
+def test_vertex_counts_rmat22_full_size():
+    # the bench configuration: n = 2^22 is within the 64-bit bound
+    gd = golden("rmat")
+    if gd is None:
+        pytest.skip("R-MAT oracle counts not generated yet")
+    g = C.rmat22()
+    counts, V = gpu_vertex(g, validate=False)
+    assert counts == [int(x) for x in gd["counts"]]
+    check_vertex_sums(g, counts, V)
+    d = g.degrees()
+    iso = np.nonzero(d == 0)[0][:5]
+    # an isolated vertex v extends each 3-subset of G - v by one independent
+    # vertex; G - v has G's triangles and 2-stars, and G's 1-edge 3-subsets
+    # minus the m that contain v
+    for v in iso:
+        r = V[v].astype(object)
+        assert r[0] == 0 and r[2] == 0 and r[3] == 0 and r[4] == counts[0]
+        assert r[12] == counts[2] and r[13] == counts[3] and r[15] == counts[4] - counts[0]
+    eu, ev = oracle.edges(g)
+    for v in _sampled_vertices(g, 30, 29)[:12]:
+        sel = (eu == v) | (ev == v)
+        if sel.any() and d[v] < 2000:
+            T, _, _ = oracle.per_edge(g, eu[sel], ev[sel])
+            assert int(V[v, 2]) == int(T.sum()) // 2
+
+
+def test_vertex_counts_reject_too_many_vertices():
+    import torch
+
+    n = 4_900_000  # C(n - 1, 3) > 2^64
+    rp = torch.zeros(n + 1, dtype=torch.int32, device="cuda:0")
+    col = torch.zeros(0, dtype=torch.int32, device="cuda:0")
+    with pytest.raises(gl.GraphletError) as e:
+        gl.graphlet_count_vertex(rp, col, n)
+    assert e.value.code == -5
+
+
 # ------------------------------------------------------------ edge updates
 
 

@@ -468,3 +468,95 @@ def test_edge_local_planted_mistake_is_caught():
     counts = oracle.bruteforce(g)
     s = int(L[:, 6].sum() + L[:, 7].sum() + L[:, 8].sum())
     assert counts[8] == 0 or s != 4 * counts[8]
+
+
+# ------------------------------------------------------------ per-vertex counts
+
+
+def _vertex_graphs():
+    rng = np.random.default_rng(808)
+    out = [graphgen.from_edges(1, []), graphgen.from_edges(5, []),
+           graphgen.from_edges(2, [(0, 1)]), graphgen.from_edges(3, [(0, 1)])]
+    for _ in range(10):
+        n = int(rng.integers(4, 22))
+        p = float(rng.random())
+        iu = np.triu_indices(n, 1)
+        mask = rng.random(len(iu[0])) < p
+        out.append(graphgen.from_edges(n, list(zip(iu[0][mask], iu[1][mask]))))
+    out.append(graphgen.from_edges(7, [(a, b) for a in range(7) for b in range(a + 1, 7)]))
+    out.append(graphgen.from_edges(9, [(0, i) for i in range(1, 9)]))
+    out.append(graphgen.from_edges(9, [(i, (i + 1) % 9) for i in range(9)]))
+    out.append(graphgen.from_edges(10, [(2 * i, 2 * i + 1) for i in range(5)]))
+    out.append(graphgen.from_edges(9, [(a, b) for a in range(4) for b in range(4, 9)]))
+    return out
+
+
+N_VERTEX_GRAPHS = 19
+
+
+@pytest.mark.parametrize("gi", range(N_VERTEX_GRAPHS))
+def test_vertex_two_routes_agree(gi):
+    # subset enumeration credited to members == g(G) - g(G - v) from the
+    # identity route; the two share nothing
+    g = _vertex_graphs()[gi]
+    np.testing.assert_array_equal(oracle.vertex_bruteforce(g).astype(np.uint64),
+                                  oracle.vertex_by_deletion(g))
+
+
+@pytest.mark.parametrize("gi", range(N_VERTEX_GRAPHS))
+def test_vertex_sums(gi):
+    # each k-subset is seen once from each of its k members, and the k-subsets
+    # holding v are all classified
+    g = _vertex_graphs()[gi]
+    n = g.n
+    V = oracle.vertex_bruteforce(g)
+    counts = oracle.bruteforce(g)
+    for c in range(17):
+        assert int(V[:, c].sum()) == oracle.CLASS_K[c] * counts[c], oracle.NAMES[c]
+    assert (V[:, :2].sum(1) == n - 1).all()
+    assert (V[:, 2:6].sum(1) == comb(n - 1, 2)).all()
+    assert (V[:, 6:].sum(1) == comb(n - 1, 3)).all()
+
+
+def test_vertex_closed_forms():
+    def row(**kw):
+        r = [0] * 17
+        for k, v in kw.items():
+            r[IDX[k]] = v
+        return r
+
+    # K_n: every subset is a clique
+    n = 7
+    V = oracle.vertex_bruteforce(
+        graphgen.from_edges(n, [(a, b) for a in range(n) for b in range(a + 1, n)]))
+    assert all(list(r) == row(g2_1=n - 1, g3_1=comb(n - 1, 2), g4_1=comb(n - 1, 3)) for r in V)
+    # star with L leaves: the centre sees stars only, a leaf also independent sets
+    L = 8
+    V = oracle.vertex_bruteforce(graphgen.from_edges(L + 1, [(0, i) for i in range(1, L + 1)]))
+    assert list(V[0]) == row(g2_1=L, g3_2=comb(L, 2), g4_5=comb(L, 3))
+    leaf = row(g2_1=1, g2_2=L - 1, g3_2=L - 1, g3_4=comb(L - 1, 2), g4_5=comb(L - 1, 2),
+               g4_11=comb(L - 1, 3))
+    assert all(list(r) == leaf for r in V[1:])
+    # perfect matching of p edges
+    p = 5
+    V = oracle.vertex_bruteforce(graphgen.from_edges(2 * p, [(2 * i, 2 * i + 1) for i in range(p)]))
+    g49 = p - 1
+    g410 = comb(2 * p - 2, 2) - (p - 1) + (p - 1) * (2 * p - 4)
+    want = row(g2_1=1, g2_2=2 * p - 2, g3_3=3 * p - 3, g3_4=comb(2 * p - 1, 2) - (3 * p - 3),
+               g4_9=g49, g4_10=g410, g4_11=comb(2 * p - 1, 3) - g49 - g410)
+    assert all(list(r) == want for r in V)
+    # cycle C_9: each vertex is in 3 two-stars and 4 four-paths
+    V = oracle.vertex_bruteforce(graphgen.from_edges(9, [(i, (i + 1) % 9) for i in range(9)]))
+    assert (V[:, IDX["g3_2"]] == 3).all() and (V[:, IDX["g4_6"]] == 4).all()
+    assert (V[:, IDX["g3_1"]] == 0).all() and (V[:, IDX["g4_4"]] == 0).all()
+
+
+def test_vertex_planted_mistake_is_caught():
+    # forgetting the subsets in which v is isolated (here: a triangle seen from
+    # an outside vertex) breaks the sum rule
+    g = graphgen.from_edges(6, [(0, 1), (1, 2), (0, 2), (3, 4)])
+    V = oracle.vertex_bruteforce(g)
+    counts = oracle.bruteforce(g)
+    assert int(V[:, IDX["g4_7"]].sum()) == 4 * counts[IDX["g4_7"]]
+    V[3:, IDX["g4_7"]] = 0
+    assert int(V[:, IDX["g4_7"]].sum()) != 4 * counts[IDX["g4_7"]]
