@@ -86,15 +86,18 @@ def measured_traffic(kernel: str, workload: str):
     return float(fields["traffic_bytes_per_launch"])
 
 
-def roofline_from_timing(t: dict):
-    """The dominant kernel, k_c4_heavy_bal (one launch, alone in its phase):
-    its algorithmic bytes (4 B per wedge it aggregates) over its device time
-    from HIP events on the library's stream."""
+def roofline_from_timing(t: dict, per_edge: bool = False):
+    """The dominant kernel, the heavy 4-cycle items (one launch, alone in its
+    phase; k_c4_heavy_bal for global counts, k_c4_heavy with per-edge
+    outputs): its algorithmic bytes (4 B per wedge it aggregates) over its
+    device time from HIP events on the library's stream."""
     ms, nbytes = t["cyc_heavy_ms"], 4 * t["wedges_heavy"]
     achieved = nbytes / (ms / 1e3) / 1e9 if ms > 0 else 0.0
     return "cyc_heavy", {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                         "traffic": None, "kernel": "k_c4_heavy_bal", "phase_ms": round(ms, 3),
+                         "traffic": None,
+                         "kernel": "k_c4_heavy" if per_edge else "k_c4_heavy_bal",
+                         "phase_ms": round(ms, 3),
                          "bytes_per_launch": nbytes,
                          "work_unit": "wedges of the heavy work items x 4 B"}
 
@@ -104,25 +107,36 @@ def run_single(args, torch, gl):
 
     builders = {"rmat22": (C.rmat22, C.RMAT), "er": (C.er, C.ER), "cl": (C.cl, C.CL)}
     build, params = builders[args.workload]
+    # the Chung-Lu configuration also writes the per-edge |Tri_e|, 4-clique
+    # and induced 4-cycle arrays
+    per_edge = args.workload == "cl"
     t0 = time.time()
     g = build()
     log(f"[bench] generated {args.workload}: n={g.n} m={g.m} in {time.time() - t0:.1f}s")
     dev = torch.device("cuda:0")
     rp = torch.from_numpy(g.row_ptr).to(dev)
     col = torch.from_numpy(g.col).to(dev)
-    ws_bytes = gl.graphlet_workspace_size(rp, col, g.n)
+    ws_bytes = gl.graphlet_workspace_size(rp, col, g.n, per_edge=per_edge)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    pe = torch.empty((3, max(g.m, 1)), dtype=torch.int64, device=dev) if per_edge else None
     log(f"[bench] workspace {ws_bytes / 2**30:.2f} GiB")
+
+    def call():
+        if per_edge:
+            return gl.graphlet_count(rp, col, g.n, per_edge=True, workspace=ws,
+                                     per_edge_out=pe)[0]
+        return gl.graphlet_count(rp, col, g.n, workspace=ws)
+
     gl.graphlet_timing_enable(True)
     counts = None
     for i in range(args.warmup):
-        counts = gl.graphlet_count(rp, col, g.n, workspace=ws)
+        counts = call()
         log(f"[bench] warmup {i} done")
     torch.cuda.synchronize()
     phase_sum = {}
     t0 = time.perf_counter()
     for i in range(args.steps):
-        c = gl.graphlet_count(rp, col, g.n, workspace=ws)
+        c = call()
         t = gl.graphlet_last_timing()
         for k, v in t.items():
             phase_sum[k] = phase_sum.get(k, 0) + v
@@ -134,7 +148,7 @@ def run_single(args, torch, gl):
     ms = dt / args.steps * 1e3
     timing = {k: v / args.steps for k, v in phase_sum.items()}
     log("[bench] phases: " + ", ".join(f"{k}={v:.3f}" for k, v in timing.items() if k.endswith("_ms")))
-    name, roof = roofline_from_timing(timing)
+    name, roof = roofline_from_timing(timing, per_edge)
     roof["traffic"] = measured_traffic(roof["kernel"], args.workload)
     value = g.m / (ms / 1e3)
     res = {
@@ -151,7 +165,9 @@ def run_single(args, torch, gl):
         "dtype": "int64/u128 (exact integer)",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": g.n, "m": g.m, "csr_sha256": g.sha256(),
-                   "params": params, "output": "17 x u128 global counts"},
+                   "params": params,
+                   "output": "17 x u128 global counts" + (
+                       " + 3 x int64[m] per-edge arrays" if per_edge else "")},
         "roofline": roof,
         "phases_ms": {k: round(v, 3) for k, v in timing.items() if k.endswith("_ms")},
         "work": {k: timing[k] for k in ("clique_entries", "wedges_light", "wedges_heavy",
@@ -407,6 +423,7 @@ def run_vertex(args, torch, gl):
     out = torch.empty((17, g.n), dtype=torch.uint64, device=dev)
     log(f"[bench] vertex: workspace {ws_bytes / 2**30:.2f} GiB")
     gl.graphlet_timing_enable(True)
+    counts = None
     for i in range(args.warmup):
         counts, V = gl.graphlet_count_vertex(rp, col, g.n, workspace=ws, out=out)
         log(f"[bench] warmup {i} done")
@@ -417,8 +434,9 @@ def run_vertex(args, torch, gl):
         c, V = gl.graphlet_count_vertex(rp, col, g.n, workspace=ws, out=out)
         for k, v in gl.graphlet_last_timing().items():
             phase_sum[k] = phase_sum.get(k, 0) + v
-        if c != counts:
+        if counts is not None and c != counts:
             raise RuntimeError("counts changed between steps")
+        counts = c
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) / args.steps * 1e3
     timing = {k: v / args.steps for k, v in phase_sum.items()}

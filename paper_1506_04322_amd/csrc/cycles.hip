@@ -28,10 +28,6 @@ namespace {
 
 __device__ __forceinline__ u64 choose2(u64 c) { return c * (c - 1) / 2; }
 
-// Upper position of the undirected edge stored at position p of N(v).
-__device__ __forceinline__ int upper_pos(const int32_t *col2, const int32_t *tpos, int p, int v) {
-  return col2[p] > v ? p : tpos[p];
-}
 
 template <bool PER_EDGE>
 __global__ __launch_bounds__(kWave) void k_c4_light(C4Args g) {
@@ -99,8 +95,8 @@ __global__ __launch_bounds__(kWave) void k_c4_light(C4Args g) {
             while (hkey[h] != y) h = (h + 1) & mask;
             const u64 c = hcnt[h];
             if (c >= 2) {
-              atomicAdd(&g.C4w[upper_pos(g.col2, g.tpos, p, sV[lo])], c - 1);
-              atomicAdd(&g.C4w[g.tpos[sQ[lo]]], c - 1);
+              atomicAdd(&g.C4w[p], c - 1);       // edge (v, y) at v's entry for y
+              atomicAdd(&g.C4w[sQ[lo]], c - 1);  // edge (x, v) at x's entry for v
             }
           }
         }
@@ -113,105 +109,6 @@ __global__ __launch_bounds__(kWave) void k_c4_light(C4Args g) {
         hkey[h] = -1;
         hcnt[h] = 0;
       }
-    }
-    __syncthreads();
-  }
-  const u128 s = block_sum_u128(acc, red);
-  if (threadIdx.x == 0 && s) atomic_add_u128(g.c4ni, s);
-}
-
-template <bool PER_EDGE>
-__global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy(C4Args g) {
-  __shared__ uint32_t cnt[kChunkWords];
-  __shared__ u64 red[32];
-  __shared__ int s_item;
-  const int tid = threadIdx.x;
-  const int64_t nitems = *g.nitems;
-  int32_t *cur = g.gcur + (size_t)blockIdx.x * g.lmax;
-  int32_t *beg = PER_EDGE ? g.gbeg + (size_t)blockIdx.x * g.lmax : nullptr;
-  u64 *cacc = PER_EDGE ? g.gacc + (size_t)blockIdx.x * g.lmax : nullptr;
-  u128 acc = 0;
-  while (true) {
-    if (tid == 0) s_item = (int)atomicAdd(g.queue, 1ull);
-    __syncthreads();
-    const int item = s_item;
-    __syncthreads();
-    if (item >= nitems) break;
-    const int4 it = g.items[item];
-    const int x = it.x, ya = it.y, yb = it.z;
-    const int Lx = g.rp2[x], nL = g.lcnt[x];
-    // 2 x 16-bit counters per word while no count can reach 2^16
-    const bool packed = nL < 65536;
-    const int K = packed ? 2 * kChunkWords : kChunkWords;
-    for (int i = tid; i < nL; i += kC4HeavyBlock) {
-      const int q = Lx + i;
-      const int s = g.rp2[g.col2[q]];
-      const int e = g.tpos[q];
-      cur[i] = s + lower_bound_dev<int32_t>(g.col2 + s, e - s, ya);
-      if (PER_EDGE) cacc[i] = 0;
-    }
-    __syncthreads();
-    for (int c0 = ya; c0 < yb; c0 += K) {
-      const int c1 = min(c0 + K, yb);
-      for (int w = tid; w < kChunkWords; w += kC4HeavyBlock) cnt[w] = 0;
-      __syncthreads();
-      for (int i = tid; i < nL; i += kC4HeavyBlock) {
-        const int e = g.tpos[Lx + i];
-        int p = cur[i];
-        if (PER_EDGE) beg[i] = p;
-        // four independent loads per round keep more requests in flight
-        while (p < e) {
-          const int y0 = g.col2[p];
-          const int y1 = p + 1 < e ? g.col2[p + 1] : INT32_MAX;
-          const int y2 = p + 2 < e ? g.col2[p + 2] : INT32_MAX;
-          const int y3 = p + 3 < e ? g.col2[p + 3] : INT32_MAX;
-          int ys[4] = {y0, y1, y2, y3};
-          bool stop = false;
-#pragma unroll
-          for (int r = 0; r < 4; r++) {
-            const int y = ys[r];
-            if (y >= c1) {
-              stop = true;
-              break;
-            }
-            const int d = y - c0;
-            if (packed) atomicAdd(&cnt[d >> 1], (d & 1) ? 65536u : 1u);
-            else atomicAdd(&cnt[d], 1u);
-            p++;
-          }
-          if (stop) break;
-        }
-        cur[i] = p;
-      }
-      __syncthreads();
-      if (PER_EDGE) {
-        for (int i = tid; i < nL; i += kC4HeavyBlock) {
-          const int v = g.col2[Lx + i];
-          u64 credit = 0;
-          for (int p = beg[i]; p < cur[i]; p++) {
-            const int d = g.col2[p] - c0;
-            const u64 c = packed ? ((cnt[d >> 1] >> ((d & 1) * 16)) & 0xffffu) : cnt[d];
-            if (c >= 2) {
-              atomicAdd(&g.C4w[upper_pos(g.col2, g.tpos, p, v)], c - 1);
-              credit += c - 1;
-            }
-          }
-          cacc[i] += credit;
-        }
-        __syncthreads();
-      }
-      u64 part = 0;
-      for (int w = tid; w < kChunkWords; w += kC4HeavyBlock) {
-        const uint32_t val = cnt[w];
-        if (packed) part += choose2(val & 0xffffu) + choose2(val >> 16);
-        else part += choose2(val);
-      }
-      acc += (u128)part;
-      __syncthreads();
-    }
-    if (PER_EDGE) {
-      for (int i = tid; i < nL; i += kC4HeavyBlock)
-        if (cacc[i]) atomicAdd(&g.C4w[g.tpos[Lx + i]], cacc[i]);
     }
     __syncthreads();
   }
@@ -257,14 +154,19 @@ __device__ void scan_excl(int32_t *A, int k, int32_t *wsum) {
   __syncthreads();
 }
 
-// Medium x (global mode): one workgroup per vertex, c(x, .) in an LDS hash
-// of kMediumSlots slots (keys, and 16-bit counts packed two per word: every
+// Medium x: one workgroup per vertex, c(x, .) in an LDS hash of
+// kMediumSlots slots (keys, and 16-bit counts packed two per word: every
 // count is at most W(x) <= kMediumWedges < 2^16); wedges enumerated flat over
 // batches of lower neighbours so every thread reads a share of each batch.
+// Per-edge mode walks the wedges a second time once the counts are final:
+// wedge x - v - y adds c(x, y) - 1 to edge (v, y) and, summed over the
+// wedges of v, to edge (x, v).
+template <bool PER_EDGE>
 __global__ __launch_bounds__(kMediumBlock) void k_c4_medium(C4Args g) {
   __shared__ int32_t hkey[kMediumSlots];
   __shared__ uint32_t hcnt[kMediumSlots / 2];
   __shared__ int32_t sPre[kMediumBlock + 1], sStart[kMediumBlock], sums[kMediumBlock / kWave + 1];
+  __shared__ u64 credit[PER_EDGE ? kMediumBlock : 1];
   __shared__ u64 red[32];
   const int tid = threadIdx.x;
   for (int h = tid; h < kMediumSlots; h += kMediumBlock) hkey[h] = -1;
@@ -302,6 +204,36 @@ __global__ __launch_bounds__(kMediumBlock) void k_c4_medium(C4Args g) {
         }
       }
       __syncthreads();
+    }
+    if (PER_EDGE) {
+      for (int b = 0; b < nL; b += kMediumBlock) {
+        const int nb = min(kMediumBlock, nL - b);
+        if (tid < nb) {
+          const int q = Lx + b + tid;
+          const int s = g.rp2[g.col2[q]];
+          sStart[tid] = s;
+          sPre[tid] = g.tpos[q] - s;
+          credit[tid] = 0;
+        }
+        __syncthreads();
+        scan_excl<kMediumBlock>(sPre, nb, sums);
+        const int total = sPre[nb];
+        for (int t = tid; t < total; t += kMediumBlock) {
+          const int o = upper_index_dev<int32_t>(sPre, nb, t);
+          const int p = sStart[o] + (t - sPre[o]);
+          const int y = g.col2[p];
+          int h = (int)(((u64)((uint32_t)y * 2654435761u) * (u64)hs) >> 32);
+          while (hkey[h] != y) h = h + 1 == hs ? 0 : h + 1;  // y was inserted above
+          const uint32_t c = (hcnt[h >> 1] >> ((h & 1) * 16)) & 0xffffu;
+          if (c >= 2) {
+            atomicAdd(&g.C4w[p], (u64)(c - 1));
+            atomicAdd(&credit[o], (u64)(c - 1));
+          }
+        }
+        __syncthreads();
+        if (tid < nb && credit[tid]) atomicAdd(&g.C4w[Lx + b + tid], credit[tid]);
+        __syncthreads();
+      }
     }
     u64 part = 0;
     for (int h = tid; h < hs; h += kMediumBlock) {
@@ -348,9 +280,15 @@ __device__ __forceinline__ int count_below(const int32_t *col2, int p, int e, in
 // threads read neighbouring entries.  Counters are zero between chunks: a
 // chunk with few wedges is summed and cleared by revisiting its wedges (the
 // first visitor of a counter takes its value), a dense one by a sweep.
+// Per-edge mode revisits each chunk's wedges once its counts are complete
+// (before they are cleared): wedge x - v - y adds c(x, y) - 1 to edge (v, y)
+// and to edge (x, v), each at a directed entry (folded into the edge's upper
+// position afterwards).
+template <bool PER_EDGE>
 __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
   __shared__ uint32_t cnt[kChunkWords];
   __shared__ int32_t vpre[kHeavyGroup + 1], vcur[kHeavyGroup], sums[kC4HeavyBlock / kWave + 1];
+  __shared__ int32_t vE[PER_EDGE ? kHeavyGroup : 1];
   __shared__ u64 red[32];
   __shared__ int s_item, s_nact, s_nsel;
   constexpr int RUN = 8;
@@ -360,6 +298,10 @@ __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
   int32_t *end = g.gbeg + (size_t)blockIdx.x * g.lmax;
   int32_t *nxt = g.gnext + (size_t)blockIdx.x * g.lmax;
   int32_t *sel = g.gsel + (size_t)blockIdx.x * g.lmax;
+  // per-edge: list index of each active list and its run start in the
+  // current chunk
+  int32_t *vid = PER_EDGE ? g.gvid + (size_t)blockIdx.x * g.lmax : nullptr;
+  int32_t *cb = PER_EDGE ? g.gcb + (size_t)blockIdx.x * g.lmax : nullptr;
   for (int w = tid; w < kChunkWords; w += kC4HeavyBlock) cnt[w] = 0;
   u128 acc = 0;
   while (true) {
@@ -399,6 +341,7 @@ __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
         cur[o] = c;
         end[o] = e;
         nxt[o] = y;
+        if (PER_EDGE) vid[o] = i;
       }
     }
     __syncthreads();
@@ -457,10 +400,58 @@ __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
         for (int j = tid; j < nG; j += kC4HeavyBlock) {
           const int i = sel[g0 + j];
           const int p = vcur[j] + (vpre[j + 1] - vpre[j]);
+          if (PER_EDGE) cb[i] = vcur[j];
           cur[i] = p;
           nxt[i] = p < end[i] ? g.col2[p] : INT32_MAX;
         }
         __syncthreads();
+      }
+      if (PER_EDGE) {
+        // The chunk's counts are complete: credit its wedges, group by group
+        // (the last group leaves vcur / vpre as the counting pass did).
+        // Consecutive threads take consecutive wedges, so the credits of a
+        // run land on consecutive entries; the credits of edge (x, v) are
+        // summed over each wave's run of v first.
+        for (int g0 = 0; g0 < nS; g0 += kHeavyGroup) {
+          const int nG = min(kHeavyGroup, nS - g0);
+          for (int j = tid; j < nG; j += kC4HeavyBlock) {
+            const int i = sel[g0 + j];
+            vcur[j] = cb[i];
+            vpre[j] = cur[i] - cb[i];
+            vE[j] = Lx + vid[i];
+          }
+          __syncthreads();
+          scan_excl<kC4HeavyBlock>(vpre, nG, sums);
+          const int F = vpre[nG];
+          for (int f0 = 0; f0 < F; f0 += kC4HeavyBlock) {
+            const int f = f0 + tid;
+            int j = -1;
+            u64 cr = 0;
+            if (f < F) {
+              j = upper_index_dev<int32_t>(vpre, nG, f);
+              const int p = vcur[j] + (f - vpre[j]);
+              const int d = g.col2[p] - c0;
+              const uint32_t c = packed ? (cnt[d >> 1] >> ((d & 1) * 16)) & 0xffffu : cnt[d];
+              if (c >= 2) {
+                cr = c - 1;
+                atomicAdd(&g.C4w[p], cr);  // edge (v, y) at v's entry for y
+              }
+            }
+            // segmented sum over the wave's lanes with the same list (lanes
+            // hold increasing f, so each list is a contiguous run of lanes)
+            const int lane = lane_id();
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) {
+              const u64 o = __shfl_up(cr, off, kWave);
+              const int jo = __shfl_up(j, off, kWave);
+              if (lane >= off && jo == j) cr += o;
+            }
+            const int jn = __shfl_down(j, 1, kWave);
+            if (j >= 0 && cr && (lane == kWave - 1 || jn != j))
+              atomicAdd(&g.C4w[vE[j]], cr);  // edge (x, v) at x's entry for v
+          }
+          __syncthreads();
+        }
       }
       u64 part = 0;
       if (nS <= kHeavyGroup && Fall <= kSparseChunk) {
@@ -659,7 +650,26 @@ __global__ __launch_bounds__(256) void k_hub_long(HubArgs g) {
   if (threadIdx.x == 0 && s) atomic_add_u128(g.c4ni, s);
 }
 
+// Per-edge mode: the 4-cycle credits of an edge were added at either of its
+// two directed entries; the lower one is folded into the upper position,
+// where the per-edge outputs are read.
+__global__ void k_c4_fold(const u64 *ekeys, const int32_t *col2, const int32_t *tpos, int64_t nnz,
+                          int B, u64 *C4w) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nnz) return;
+  const int32_t x = (int32_t)(ekeys[p] >> B);
+  if (col2[p] > x) C4w[p] += C4w[tpos[p]];
+}
+
 }  // namespace
+
+int launch_c4_fold(const u64 *ekeys, const int32_t *col2, const int32_t *tpos, int64_t nnz, int B,
+                   u64 *C4w, hipStream_t s) {
+  if (nnz <= 0) return GC_OK;
+  k_c4_fold<<<grid1d(nnz, 256), 256, 0, s>>>(ekeys, col2, tpos, nnz, B, C4w);
+  GC_TRY_HIP(hipGetLastError());
+  return GC_OK;
+}
 
 int launch_dense_slab(const HubArgs &g, hipStream_t s) {
   if (g.nslab <= 0) return GC_OK;
@@ -675,10 +685,11 @@ int launch_dense_slab(const HubArgs &g, hipStream_t s) {
   return GC_OK;
 }
 
-int launch_cycles_medium(C4Args g, hipStream_t s) {
+int launch_cycles_medium(C4Args g, bool per_edge, hipStream_t s) {
   if (g.nlist <= 0) return GC_OK;
   const unsigned grid = (unsigned)std::min(g.nlist, 16384);
-  k_c4_medium<<<grid, kMediumBlock, 0, s>>>(g);
+  if (per_edge) k_c4_medium<true><<<grid, kMediumBlock, 0, s>>>(g);
+  else k_c4_medium<false><<<grid, kMediumBlock, 0, s>>>(g);
   GC_TRY_HIP(hipGetLastError());
   return GC_OK;
 }
@@ -694,8 +705,8 @@ int launch_cycles_light(C4Args g, bool per_edge, hipStream_t s) {
 
 int launch_cycles_heavy(C4Args g, int slots, bool per_edge, hipStream_t s) {
   if (slots <= 0) return GC_OK;
-  if (per_edge) k_c4_heavy<true><<<slots, kC4HeavyBlock, 0, s>>>(g);
-  else k_c4_heavy_bal<<<slots, kC4HeavyBlock, 0, s>>>(g);
+  if (per_edge) k_c4_heavy_bal<true><<<slots, kC4HeavyBlock, 0, s>>>(g);
+  else k_c4_heavy_bal<false><<<slots, kC4HeavyBlock, 0, s>>>(g);
   GC_TRY_HIP(hipGetLastError());
   return GC_OK;
 }

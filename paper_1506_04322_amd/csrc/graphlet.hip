@@ -85,8 +85,7 @@ void alloc_fixed(Arena &a, const Plan &P, Fixed &f) {
   p.c4l = a.take<int32_t>(n);
   p.c4m = a.take<int32_t>(n);
   p.c4h = a.take<int32_t>(n);
-  // the medium class exists in global mode only
-  p.medium_max = P.per_edge ? kLightWedges : kMediumWedges;
+  p.medium_max = kMediumWedges;
   f.T = a.take<uint32_t>(nnz);
   f.nstep3 = (int)std::min<int64_t>(kStep3Grid, std::max<int64_t>(1, (nnz + 255) / 256));
   f.partials = a.take<u64>((size_t)f.nstep3 * kAcc * 2);
@@ -131,8 +130,7 @@ struct Dyn {
   u64 *gR;
   int32_t *gI;
   u64 *gA;
-  int32_t *gcur, *gbeg, *gnext, *gsel;
-  u64 *gacc;
+  int32_t *gcur, *gbeg, *gnext, *gsel, *gvid, *gcb;
   int4 *items;
   u64 *hkeys, *hkeys_alt;
   int64_t *pcount;
@@ -149,9 +147,10 @@ void alloc_dyn(Arena &a, const Plan &P, const DynNeed &d, Dyn &y) {
   const size_t lm = (size_t)std::max(d.lmax, 1), sl = (size_t)std::max(d.slots, 1);
   y.gcur = a.take<int32_t>(sl * lm);
   y.gbeg = a.take<int32_t>(sl * lm);
-  y.gnext = P.per_edge ? nullptr : a.take<int32_t>(sl * lm);
-  y.gsel = P.per_edge ? nullptr : a.take<int32_t>(sl * lm);
-  y.gacc = P.per_edge ? a.take<u64>(sl * lm) : nullptr;
+  y.gnext = a.take<int32_t>(sl * lm);
+  y.gsel = a.take<int32_t>(sl * lm);
+  y.gvid = P.per_edge ? a.take<int32_t>(sl * lm) : nullptr;
+  y.gcb = P.per_edge ? a.take<int32_t>(sl * lm) : nullptr;
   y.items = a.take<int4>((size_t)std::max<int64_t>(d.items_cap, 1));
   const size_t nh = (size_t)std::max(d.nheavy, 1);
   y.hkeys = a.take<u64>(nh);
@@ -509,7 +508,7 @@ int run(const gc_csr *G, gc_u128 out17[17], int64_t *per_edge_out, int64_t *loca
     C4Args cm = c4;
     cm.list = pp.c4m;
     cm.nlist = hc.c4_medium;
-    GC_TRY(launch_cycles_medium(cm, s));
+    GC_TRY(launch_cycles_medium(cm, P.per_edge, s));
   }
   ev.record(4, s);
   for (int b = 0; b < ndense; b += kDenseSlab) {
@@ -533,10 +532,12 @@ int run(const gc_csr *G, gc_u128 out17[17], int64_t *per_edge_out, int64_t *loca
     c4.gbeg = dy.gbeg;
     c4.gnext = dy.gnext;
     c4.gsel = dy.gsel;
-    c4.gacc = dy.gacc;
+    c4.gvid = dy.gvid;
+    c4.gcb = dy.gcb;
     c4.lmax = std::max(dn.lmax, 1);
     GC_TRY(launch_cycles_heavy(c4, dn.slots, P.per_edge, s));
   }
+  if (P.per_edge) GC_TRY(launch_c4_fold(pp.esorted, pp.col2, pp.tpos, nnz, P.B, f.C4w, s));
   ev.record(6, s);
 
   // -- per-edge 4-cliques and D_e (needs final |Tri|)
@@ -545,7 +546,7 @@ int run(const gc_csr *G, gc_u128 out17[17], int64_t *per_edge_out, int64_t *loca
     GC_TRY(cliques(true));
   }
   if (P.local)
-    GC_TRY(launch_vertex_sums(pp.esorted, pp.col2, f.T, pp.deg2, nnz, P.B, f.tv, f.sv, s));
+    GC_TRY(launch_vertex_sums(pp.rp2, pp.col2, pp.lcnt, pp.tpos, f.T, pp.deg2, n, f.tv, f.sv, s));
   ev.record(7, s);
 
   // -- Step 3

@@ -166,16 +166,17 @@ struct C4Args {
   const int32_t *list;
   int nlist;
   u64 *c4ni;  // total (128-bit)
-  u64 *C4w;   // per-edge pass: 4-cycles (chords allowed) per upper position
+  u64 *C4w;   // per-edge pass: 4-cycles (chords allowed) per edge, credited at
+              // either directed entry until folded into the upper position
   const int4 *items;  // (x, y_begin, y_end, -)
   const int64_t *nitems;
   u64 *queue;
   int32_t *gcur;  // per slot: cursor per lower neighbour
-  int32_t *gbeg;  // per slot: end of each active list (global mode) or
-                  // cursor at chunk start (per-edge mode)
-  int32_t *gnext; // per slot (global mode): next entry of each active list
-  int32_t *gsel;  // per slot (global mode): lists with entries in the chunk
-  u64 *gacc;      // per slot (per-edge): credit for edge (x, v)
+  int32_t *gbeg;  // per slot: end of each active list
+  int32_t *gnext; // per slot: next entry of each active list
+  int32_t *gsel;  // per slot: lists with entries in the chunk
+  int32_t *gvid;  // per slot (per-edge): list index of each active list
+  int32_t *gcb;   // per slot (per-edge): run start of each list in the chunk
   int lmax;
 };
 
@@ -199,7 +200,11 @@ struct HubArgs {
 int launch_dense_slab(const HubArgs &g, hipStream_t s);
 
 int launch_cycles_light(C4Args g, bool per_edge, hipStream_t s);
-int launch_cycles_medium(C4Args g, hipStream_t s);
+int launch_cycles_medium(C4Args g, bool per_edge, hipStream_t s);
+// Per-edge mode: adds each edge's lower directed entry of C4w into its upper
+// position.
+int launch_c4_fold(const u64 *ekeys, const int32_t *col2, const int32_t *tpos, int64_t nnz, int B,
+                   u64 *C4w, hipStream_t s);
 int launch_cycles_heavy(C4Args g, int slots, bool per_edge, hipStream_t s);
 
 // ---------------------------------------------------------------- Step 3
@@ -227,10 +232,11 @@ struct S3Args {
 };
 
 constexpr int kLocal = 17;
-// Per vertex by rank: tv += T_e over incident edges (twice its triangles),
-// sv += deg of every neighbour.
-int launch_vertex_sums(const u64 *ekeys, const int32_t *col2, const uint32_t *T,
-                       const int32_t *deg2, int64_t nnz, int B, u64 *tv, u64 *sv, hipStream_t s);
+// Per vertex by rank: tv = sum of T_e over incident edges (twice its
+// triangles), sv = sum of the neighbours' degrees.
+int launch_vertex_sums(const int32_t *rp2, const int32_t *col2, const int32_t *lcnt,
+                       const int32_t *tpos, const uint32_t *T, const int32_t *deg2, int64_t n,
+                       u64 *tv, u64 *sv, hipStream_t s);
 
 // Per-vertex counts from the per-edge arrays of the local-vector pass.
 struct VxArgs {

@@ -137,15 +137,27 @@ __global__ void k_step3_final(const u64 *partials, int nblocks, DevAcc *acc) {
   }
 }
 
-__global__ void k_vertex_sums(const u64 *ekeys, const int32_t *col2, const uint32_t *T,
-                              const int32_t *deg2, int64_t nnz, int B, u64 *tv, u64 *sv) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nnz) return;
-  const int32_t x = (int32_t)(ekeys[p] >> B), y = col2[p];
-  atomicAdd(&sv[x], (u64)deg2[y]);
-  if (y > x) {
-    atomicAdd(&tv[x], (u64)T[p]);
-    atomicAdd(&tv[y], (u64)T[p]);
+// One wave per vertex x: tv[x] = sum of |Tri_e| over x's edges (read at each
+// edge's upper position), sv[x] = sum of the neighbours' degrees.
+__global__ __launch_bounds__(256) void k_vertex_sums(const int32_t *rp2, const int32_t *col2,
+                                                     const int32_t *lcnt, const int32_t *tpos,
+                                                     const uint32_t *T, const int32_t *deg2,
+                                                     int64_t n, u64 *tv, u64 *sv) {
+  const int64_t waves = (int64_t)gridDim.x * (256 / kWave);
+  for (int64_t x = (int64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave; x < n;
+       x += waves) {
+    const int32_t r0 = rp2[x], r1 = rp2[x + 1], nl = lcnt[x];
+    u64 t = 0, d = 0;
+    for (int q = r0 + lane_id(); q < r1; q += kWave) {
+      d += (u64)deg2[col2[q]];
+      t += T[q - r0 < nl ? tpos[q] : q];
+    }
+    t = wave_sum_u64(t);
+    d = wave_sum_u64(d);
+    if (lane_id() == 0) {
+      tv[x] = t;
+      sv[x] = d;
+    }
   }
 }
 
@@ -168,10 +180,12 @@ int launch_step3(S3Args g, int grid, bool per_edge, hipStream_t s) {
   return GC_OK;
 }
 
-int launch_vertex_sums(const u64 *ekeys, const int32_t *col2, const uint32_t *T,
-                       const int32_t *deg2, int64_t nnz, int B, u64 *tv, u64 *sv, hipStream_t s) {
-  if (nnz <= 0) return GC_OK;
-  k_vertex_sums<<<grid1d(nnz, 256), 256, 0, s>>>(ekeys, col2, T, deg2, nnz, B, tv, sv);
+int launch_vertex_sums(const int32_t *rp2, const int32_t *col2, const int32_t *lcnt,
+                       const int32_t *tpos, const uint32_t *T, const int32_t *deg2, int64_t n,
+                       u64 *tv, u64 *sv, hipStream_t s) {
+  if (n <= 0) return GC_OK;
+  const unsigned grid = (unsigned)std::min<int64_t>((n + 3) / 4, 16384);
+  k_vertex_sums<<<grid, 256, 0, s>>>(rp2, col2, lcnt, tpos, T, deg2, n, tv, sv);
   GC_TRY_HIP(hipGetLastError());
   return GC_OK;
 }
