@@ -67,6 +67,36 @@ __device__ __forceinline__ int hfind(const int32_t *H, const int32_t *U, uint32_
   }
 }
 
+// Candidate entries (the upper lists of the kept rows, concatenated; row o
+// starts at P[o] and reads list position V[o]) are taken in slabs of
+// kWave * RUN per wave: in step r, lane L takes candidate s0 + r * kWave + L,
+// so the lanes of each load and of each per-entry atomic touch consecutive
+// entries.  Each lane finds its row by binary search between the rows of
+// the slab's first and last candidates.  pos[r] = -1 past the end.
+template <int RUN>
+__device__ __forceinline__ void slab_positions(const int32_t *P, const int32_t *V,
+                                               const int32_t *rid, int nr, int total, int s0,
+                                               int (&pos)[RUN], int (&row)[RUN]) {
+  const int lane = lane_id();
+  const int ia = upper_index_dev<int32_t>(P, nr, s0);
+  const int ib = upper_index_dev<int32_t>(P, nr, min(s0 + kWave * RUN, total) - 1) + 1;
+#pragma unroll
+  for (int r = 0; r < RUN; r++) {
+    const int t = s0 + r * kWave + lane;
+    pos[r] = -1;
+    if (t < total) {
+      int lo = ia, hi = ib;  // P[ia] <= t < P[ib]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (P[mid] <= t) lo = mid;
+        else hi = mid;
+      }
+      pos[r] = V[lo] + (t - P[lo]);
+      row[r] = rid[lo];
+    }
+  }
+}
+
 // Row i of the triangular layout holds words [i >> 6, W) of the upper half.
 __device__ __forceinline__ int tri_off(int i, int W) {
   const int q = i >> 6;
@@ -137,19 +167,9 @@ __global__ __launch_bounds__(BLOCK) void k_tk_up(TkArgs g) {
     // Build: every entry x of U(U_i) that lies in U(u) is a triangle.  Each
     // thread takes RUN consecutive entries: positions first, then all loads,
     // then the LDS work, so RUN reads are in flight per thread.
-    for (int t0 = tid * RUN; t0 < total; t0 += BLOCK * RUN) {
-      int i = upper_index_dev<int32_t>(P, nr, t0);
+    for (int s0 = (tid / kWave) * kWave * RUN; s0 < total; s0 += BLOCK * RUN) {
       int pos[RUN], row[RUN], xv[RUN];
-#pragma unroll
-      for (int r = 0; r < RUN; r++) {
-        const int t = t0 + r;
-        pos[r] = -1;
-        if (t < total) {
-          while (P[i + 1] <= t) i++;
-          pos[r] = V[i] + (t - P[i]);
-          row[r] = rid[i];
-        }
-      }
+      slab_positions<RUN>(P, V, rid, nr, total, s0, pos, row);
 #pragma unroll
       for (int r = 0; r < RUN; r++) xv[r] = pos[r] >= 0 ? g.col2[pos[r]] : -1;
 #pragma unroll
@@ -197,6 +217,124 @@ __global__ __launch_bounds__(BLOCK) void k_tk_up(TkArgs g) {
   }
   const u128 s = block_sum_u128(k4acc, red);
   if (threadIdx.x == 0 && s) atomic_add_u128(g.k4, s);
+}
+
+// ------------------------------------------------------------ per-edge mode
+
+// Per-edge pass (|Tri| is final): the 4-cliques through every local edge and
+// the D_e terms, with U(u) hashed and candidates read RUN at a time as in
+// k_tk_up.  Pass 1 builds the symmetric local adjacency (rows of W words,
+// in LDS, or in a per-workgroup global slot when GR); pass 2 revisits the
+// candidates and, for every local edge (U_i, U_j):
+//   c = |N(U_i) n N(U_j) n U(u)| (AND + popcount of the two rows) goes to
+//     the edge itself, and (halved at the end: each clique {u, U_i, U_j, U_l}
+//     is seen from two local edges at U_i) to edges (u, U_i) and (u, U_j);
+//   |Tri(u,U_i)| + |Tri(u,U_j)| - 2 goes to D of the edge, and
+//   |Tri(u,U_j)| + |Tri(U_i,U_j)| - 2 to D of (u, U_i) (and symmetrically).
+template <int BLOCK, int KCAP, int HS, bool GR>
+__global__ __launch_bounds__(BLOCK) void k_tk_pe(TkArgs g) {
+  constexpr int WC = (KCAP + 63) / 64;
+  constexpr int RUN = 8;
+  __shared__ int32_t U[KCAP], V[KCAP], P[KCAP + 1], rid[KCAP], H[HS], sums[BLOCK];
+  __shared__ uint32_t Tu[KCAP], A1[KCAP];
+  __shared__ u64 A2[KCAP];
+  __shared__ u64 Rl[GR ? 1 : KCAP * WC];
+  __shared__ int nrows;
+  const int tid = threadIdx.x;
+  u64 *R = Rl;
+  if (GR) {
+    const size_t km = (size_t)g.kmax;
+    R = g.gR + (size_t)blockIdx.x * km * ((km + 63) / 64);
+  }
+  for (int it = blockIdx.x; it < g.nlist; it += gridDim.x) {
+    const int u = g.list[it];
+    const int k = g.ucnt[u];
+    const int base = g.ustart[u];
+    const int W = (k + 63) >> 6;
+    int hs = 64;
+    while (hs < 4 * k && hs < HS) hs <<= 1;
+    const int hbits = __ffs(hs) - 1;
+    const uint32_t mask = (uint32_t)hs - 1;
+    for (int i = tid; i < k; i += BLOCK) {
+      U[i] = g.col2[base + i];
+      Tu[i] = g.T[base + i];
+      A1[i] = 0;
+      A2[i] = 0;
+    }
+    for (int h = tid; h < hs; h += BLOCK) H[h] = 0;
+    for (int w = tid; w < k * W; w += BLOCK) R[w] = 0;
+    if (tid == 0) nrows = 0;
+    __syncthreads();
+    for (int i0 = 0; i0 < k; i0 += BLOCK) {
+      const int i = i0 + tid;
+      int len = 0, v = 0;
+      if (i < k) {
+        v = U[i];
+        len = g.ucnt[v];
+        uint32_t h = hslot(v, hbits);
+        while (atomicCAS(&H[h], 0, i + 1) != 0) h = (h + 1) & mask;
+      }
+      const bool keep = len > 0;
+      const u64 m = __ballot(keep);
+      int b = 0;
+      if (lane_id() == 0 && m) b = atomicAdd(&nrows, __popcll(m));
+      b = __shfl(b, 0, kWave);
+      if (keep) {
+        const int o = b + __popcll(m & lanemask_lt());
+        rid[o] = i;
+        V[o] = g.ustart[v];
+        P[o] = len;
+      }
+    }
+    __syncthreads();
+    const int nr = nrows;
+    block_scan_excl<BLOCK>(P, nr, sums);
+    const int total = P[nr];
+    for (int pass = 0; pass < 2; pass++) {
+      for (int s0 = (tid / kWave) * kWave * RUN; s0 < total; s0 += BLOCK * RUN) {
+        int pos[RUN], row[RUN], xv[RUN];
+        slab_positions<RUN>(P, V, rid, nr, total, s0, pos, row);
+#pragma unroll
+        for (int r = 0; r < RUN; r++) xv[r] = pos[r] >= 0 ? g.col2[pos[r]] : -1;
+#pragma unroll
+        for (int r = 0; r < RUN; r++) {
+          if (pos[r] < 0) continue;
+          const int j = hfind(H, U, mask, hbits, xv[r]);
+          if (j < 0) continue;
+          const int ir = row[r];  // j > ir: U(U_i) lies above U_i
+          if (pass == 0) {
+            atomicOr(&R[(size_t)ir * W + (j >> 6)], 1ull << (j & 63));
+            atomicOr(&R[(size_t)j * W + (ir >> 6)], 1ull << (ir & 63));
+            continue;
+          }
+          const u64 *Ri = R + (size_t)ir * W, *Rj = R + (size_t)j * W;
+          uint32_t c = 0;
+          for (int z = 0; z < W; z++) c += (uint32_t)__popcll(Ri[z] & Rj[z]);
+          const int p = pos[r];
+          const u64 tij = g.T[p];
+          if (c) {
+            atomicAdd(&g.K4w[p], (u64)c);
+            atomicAdd(&A1[ir], c);
+            atomicAdd(&A1[j], c);
+          }
+          atomicAdd(&g.Dw[p], (u64)Tu[ir] + Tu[j] - 2);
+          atomicAdd(&A2[ir], (u64)Tu[j] + tij - 2);
+          atomicAdd(&A2[j], (u64)Tu[ir] + tij - 2);
+          if (g.Bw) {  // local vectors: degrees of the third vertex of the triangle
+            atomicAdd(&g.Bw[p], (u64)g.deg2[u]);
+            atomicAdd(&g.Bw[base + ir], (u64)g.deg2[U[j]]);
+            atomicAdd(&g.Bw[base + j], (u64)g.deg2[U[ir]]);
+          }
+        }
+      }
+      __syncthreads();
+    }
+    for (int i = tid; i < k; i += BLOCK) {
+      if (A1[i]) atomicAdd(&g.K4w[base + i], (u64)(A1[i] / 2));
+      if (A2[i]) atomicAdd(&g.Dw[base + i], A2[i]);
+    }
+    __syncthreads();
+  }
 }
 
 // ------------------------------------------------------------ symmetric rows
@@ -292,21 +430,6 @@ __device__ void tk_vertex(const TkArgs &g, int u, int32_t *U, int32_t *V, int32_
   __syncthreads();
 }
 
-template <int BLOCK, int KMAX>
-__global__ __launch_bounds__(BLOCK) void k_tk_lds_pe(TkArgs g) {
-  constexpr int WORDS = (KMAX + 63) / 64;
-  __shared__ int32_t U[KMAX], V[KMAX], P[KMAX + 1], sums[BLOCK];
-  __shared__ u64 R[KMAX * WORDS];
-  __shared__ u64 A1[KMAX], A2[KMAX];
-  __shared__ uint32_t Tu[KMAX];
-  u128 unused = 0;
-  for (int it = blockIdx.x; it < g.nlist; it += gridDim.x) {
-    const int u = g.list[it];
-    const int words = (g.ucnt[u] + 63) / 64;
-    tk_vertex<BLOCK, true>(g, u, U, V, P, R, words, sums, A1, A2, Tu, unused);
-  }
-}
-
 // Fallback for large k: rows and arrays in global memory, one slot per block.
 template <int BLOCK, bool PER_EDGE>
 __global__ __launch_bounds__(BLOCK) void k_tk_global(TkArgs g) {
@@ -347,9 +470,11 @@ int launch_cliques(TkArgs g, int bin, bool per_edge, hipStream_t s) {
     }
   } else {
     switch (bin) {
-      case 0: k_tk_lds_pe<64, kTkLim0><<<grid(65536), 64, 0, s>>>(g); break;
-      case 1: k_tk_lds_pe<256, kTkLim1><<<grid(16384), 256, 0, s>>>(g); break;
-      case 2: k_tk_lds_pe<256, kTkLim2><<<grid(4096), 256, 0, s>>>(g); break;
+      case 0: k_tk_pe<64, kTkLim0, 256, false><<<grid(65536), 64, 0, s>>>(g); break;
+      case 1: k_tk_pe<256, kTkLim1, 1024, false><<<grid(16384), 256, 0, s>>>(g); break;
+      case 2: k_tk_pe<512, kTkLim2, 2048, false><<<grid(8192), 512, 0, s>>>(g); break;
+      // rows of 1088 vertices (148 KB) do not fit beside the lists: global slot
+      case 3: k_tk_pe<1024, kTkLim3, 4096, true><<<grid(kTkGlobalSlots), 1024, 0, s>>>(g); break;
       default: k_tk_global<256, true><<<grid(kTkGlobalSlots), 256, 0, s>>>(g); break;
     }
   }
