@@ -36,7 +36,7 @@ __host__ __device__ inline int tk_class(int k) {
 // Light wedge vertices: at most this many wedges (LDS hash of <= 2048 slots).
 constexpr u64 kLightWedges = 1024;
 constexpr int kHashSlots = 2048;
-// Medium wedge vertices (global mode only): one workgroup, LDS hash of
+// Medium wedge vertices: one workgroup, LDS hash of
 // kMediumSlots slots (int32 key, 16-bit count) at load factor < 3/4.
 constexpr u64 kMediumWedges = 16384;
 constexpr int kMediumSlots = 22528;
