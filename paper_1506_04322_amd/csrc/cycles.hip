@@ -346,6 +346,72 @@ __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
     }
     __syncthreads();
     const int nA = s_nact;
+    if (!PER_EDGE && nL <= kWalkLists) {
+      // Few lower neighbours, hence few wedges per chunk: the selection,
+      // scan and cursor round trips of the general path would dominate.
+      // Each thread walks at most two active lists (nA <= nL < 2 x block),
+      // cursors in registers, four entries per round; the chunk's counters
+      // are summed and cleared by revisiting the walked runs (the first
+      // visitor of a counter takes its value).  Two barriers per chunk;
+      // counters are packed (nL < 2^16).
+      int pc[2], pe[2], nx[2];
+#pragma unroll
+      for (int r = 0; r < 2; r++) {
+        const int i = tid + r * kC4HeavyBlock;
+        pc[r] = 0;
+        pe[r] = 0;
+        nx[r] = INT32_MAX;
+        if (i < nA) {
+          pc[r] = cur[i];
+          pe[r] = end[i];
+          nx[r] = nxt[i];
+        }
+      }
+      for (int c0 = ya; c0 < yb; c0 += K) {
+        const int c1 = min(c0 + K, yb);
+        int b0[2];
+#pragma unroll
+        for (int r = 0; r < 2; r++) {
+          b0[r] = pc[r];
+          if (nx[r] >= c1) continue;
+          // entries before pc are below c0; col2[pc] = nx is in the chunk
+          int p = pc[r], nv = INT32_MAX;
+          const int e = pe[r];
+          bool done = false;
+          while (!done) {
+            int ys[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) ys[q] = p + q < e ? g.col2[p + q] : INT32_MAX;
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+              if (done) continue;
+              if (ys[q] >= c1) {
+                done = true;
+                nv = ys[q];
+              } else {
+                const int d = ys[q] - c0;
+                atomicAdd(&cnt[d >> 1], (d & 1) ? 65536u : 1u);
+                p++;
+              }
+            }
+          }
+          pc[r] = p;
+          nx[r] = nv;
+        }
+        __syncthreads();
+        u64 part = 0;
+#pragma unroll
+        for (int r = 0; r < 2; r++)
+          for (int p = b0[r]; p < pc[r]; p++) {
+            const int d = g.col2[p] - c0;
+            const int sh = (d & 1) * 16;
+            part += choose2((atomicAnd(&cnt[d >> 1], ~(0xffffu << sh)) >> sh) & 0xffffu);
+          }
+        acc += (u128)part;
+        __syncthreads();
+      }
+      continue;
+    }
     for (int c0 = ya; c0 < yb; c0 += K) {
       const int c1 = min(c0 + K, yb);
       if (tid == 0) s_nsel = 0;
