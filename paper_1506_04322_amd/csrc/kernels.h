@@ -88,6 +88,7 @@ struct Counters {
   u64 wedges_heavy;
   u64 clique_entries;
   u64 wedges_medium;
+  u64 lower_total;  // sum of |L(x)|: nnz / 2 for a symmetric CSR
 };
 
 __device__ __forceinline__ void flag_err(int32_t *err, int code) { atomicOr(err, 1 << (-code)); }

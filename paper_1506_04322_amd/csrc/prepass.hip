@@ -93,16 +93,23 @@ __global__ void k_edge_keys(const int32_t *rp, const int32_t *col, int64_t n, in
   }
 }
 
-__global__ void k_split_keys(const u64 *ekeys, int64_t nnz, int B, int32_t *col2) {
+// col2 from the sorted keys; tpos starts as the identity so that every entry
+// holds a valid position even where the CSR lacks a reverse entry.
+__global__ void k_split_keys(const u64 *ekeys, int64_t nnz, int B, int32_t *col2, int32_t *tpos) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < nnz) col2[p] = (int32_t)(ekeys[p] & ((1ull << B) - 1));
+  if (p < nnz) {
+    col2[p] = (int32_t)(ekeys[p] & ((1ull << B) - 1));
+    tpos[p] = (int32_t)p;
+  }
 }
 
 // lcnt[x] = |L(x)|, ucnt[x] = |U(x)|, ustart[x] = first upper position.
+// Also sums |L(x)| over all x (nnz / 2 for a symmetric CSR).
 __global__ void k_split_rows(const int32_t *rp2, const int32_t *col2, int64_t n, int32_t *lcnt,
-                             int32_t *ucnt, int32_t *ustart, int32_t *max_ucnt) {
+                             int32_t *ucnt, int32_t *ustart, int32_t *max_ucnt, u64 *lower_total) {
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int mx = 0;
+  u64 lsum = 0;
   if (x < n) {
     const int a = rp2[x], d = rp2[x + 1] - a;
     const int l = lower_bound_dev<int32_t>(col2 + a, d, (int32_t)x);
@@ -110,35 +117,42 @@ __global__ void k_split_rows(const int32_t *rp2, const int32_t *col2, int64_t n,
     ucnt[x] = d - l;
     ustart[x] = a + l;
     mx = d - l;
+    lsum = (u64)l;
   }
   for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, kWave));
+  lsum = wave_sum_u64(lsum);
   if (lane_id() == 0 && mx) atomicMax(max_ucnt, mx);
+  if (lane_id() == 0 && lsum) atomicAdd(lower_total, lsum);
 }
 
-// tpos[p] = position of the reverse entry (x in the list of y).  Every
-// position is written; a missing reverse entry or a self-loop is flagged and
-// points at p itself.
+// tpos[p] = position of the reverse entry (x in the list of y).  Each
+// undirected edge is searched once, from its upper entry (y > x) in the
+// lower part of y's list, and both of its entries are written.  An upper
+// entry without a reverse, or a self-loop, is flagged (and keeps tpos[p] =
+// p).  If every search succeeds, distinct upper entries find distinct lower
+// entries; with as many lower entries as upper ones (checked by the first
+// thread) every lower entry is then written exactly once.
 __global__ void k_tpos(const u64 *ekeys, const int32_t *col2, const int32_t *rp2,
-                       const int32_t *lcnt, int64_t nnz, int B, int32_t *tpos, int32_t *err) {
+                       const int32_t *lcnt, int64_t nnz, int B, const u64 *lower_total,
+                       int32_t *tpos, int32_t *err) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nnz) return;
+  if (p == 0 && 2 * *lower_total != (u64)nnz) flag_err(err, GC_EASYMMETRIC);
   const int32_t x = (int32_t)(ekeys[p] >> B);
   const int32_t y = col2[p];
-  int a, len;
-  if (y > x) {
-    a = rp2[y];
-    len = lcnt[y];
-  } else {
-    a = rp2[y] + lcnt[y];
-    len = rp2[y + 1] - a;
+  if (y < x) return;  // written from its upper entry
+  if (y == x) {
+    flag_err(err, GC_ESELFLOOP);
+    return;
   }
+  const int a = rp2[y], len = lcnt[y];
   const int q = a + lower_bound_dev<int32_t>(col2 + a, len, x);
-  if (y == x || q >= a + len || col2[q] != x) {
-    flag_err(err, y == x ? GC_ESELFLOOP : GC_EASYMMETRIC);
-    tpos[p] = (int32_t)p;
+  if (q >= a + len || col2[q] != x) {
+    flag_err(err, GC_EASYMMETRIC);
     return;
   }
   tpos[p] = q;
+  tpos[q] = (int32_t)p;
 }
 
 // W[x] = wedges x - v - y with v, y below x: sum over v in L(x) of the length
@@ -387,11 +401,11 @@ int run_prepass(PrepassArgs &p, Arena &a, hipStream_t s) {
                                                            p.ekeys, &p.acc->err);
   GC_TRY_HIP(hipGetLastError());
   GC_TRY(radix_sort_u64(p.ekeys, p.ekeys_alt, nnz, 2 * B, &p.esorted, a, s));
-  k_split_keys<<<grid1d(nnz, 256), 256, 0, s>>>(p.esorted, nnz, B, p.col2);
+  k_split_keys<<<grid1d(nnz, 256), 256, 0, s>>>(p.esorted, nnz, B, p.col2, p.tpos);
   k_split_rows<<<grid1d(n, 256), 256, 0, s>>>(p.rp2, p.col2, n, p.lcnt, p.ucnt, p.ustart,
-                                              &p.cnt->max_ucnt);
-  k_tpos<<<grid1d(nnz, 256), 256, 0, s>>>(p.esorted, p.col2, p.rp2, p.lcnt, nnz, B, p.tpos,
-                                          &p.acc->err);
+                                              &p.cnt->max_ucnt, &p.cnt->lower_total);
+  k_tpos<<<grid1d(nnz, 256), 256, 0, s>>>(p.esorted, p.col2, p.rp2, p.lcnt, nnz, B,
+                                          &p.cnt->lower_total, p.tpos, &p.acc->err);
   k_wedges<<<grid1d(nnz, 256), 256, 0, s>>>(p.esorted, p.col2, p.rp2, p.tpos, p.ucnt, nnz, B, p.W,
                                             &p.cnt->clique_entries);
   k_bins<<<grid1d(n, 256), 256, 0, s>>>(p.ucnt, p.lcnt, p.W, n, p.tk[0], p.tk[1], p.tk[2],

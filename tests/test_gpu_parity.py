@@ -206,6 +206,30 @@ def test_config3_rmat22_full_size():
     assert got[5] > 2**63  # needs the 128-bit path
 
 
+def test_config3_rmat22_per_edge_sampled():
+    # per-edge mode at full size: every 4-cycle vertex takes the light, medium
+    # or heavy route with credits (no dense slabs), every clique bin its
+    # per-edge kernel
+    gd = golden("rmat")
+    if gd is None:
+        pytest.skip("R-MAT oracle counts not generated yet")
+    g = C.rmat22()
+    got, pe = gpu_counts(g, per_edge=True, validate=False)
+    assert got == [int(x) for x in gd["counts"]]
+    assert int(pe[0].sum()) == 3 * got[2]
+    assert int(pe[1].sum()) == 6 * got[6]
+    assert int(pe[2].sum()) == 4 * got[9]
+    eu, ev = oracle.edges(g)
+    d = g.degrees()
+    rng = np.random.default_rng(57)
+    cheap = np.nonzero(d[eu] + d[ev] < 3000)[0]
+    idx = np.unique(rng.choice(cheap, 400, replace=False))
+    T, K4, C4 = oracle.per_edge(g, eu[idx], ev[idx])
+    np.testing.assert_array_equal(pe[0][idx], T)
+    np.testing.assert_array_equal(pe[1][idx], K4)
+    np.testing.assert_array_equal(pe[2][idx], C4)
+
+
 def test_dense_hub_slabs_rmat17():
     # every route of the costliest 4-cycle vertices gives the oracle's counts
     g = graphgen.rmat(17, 16, 0.57, 0.19, 0.19, 11)
@@ -505,6 +529,27 @@ def test_validation_rejects_bad_csr():
     assert call(3, [0, 1, 1, 2], [1, 0]) == -4  # 0->1 but 1 has no list entry
     assert call(2, [0, 1, 2], [5, 0]) == -4  # id out of range
     torch.cuda.synchronize()
+
+
+def test_unvalidated_asymmetric_csr_is_rejected():
+    # without GC_VALIDATE the prepass still refuses a CSR whose entries lack
+    # their reverse (reverse search from upper entries plus the count of
+    # lower entries), and every kernel stays in bounds on the way
+    import torch
+
+    cases = [
+        (3, [0, 1, 1, 2], [1, 0]),              # no reverse at all
+        (3, [0, 1, 3, 4], [1, 0, 2, 0]),        # 1->2 and 2->0 unpaired
+        (4, [0, 2, 3, 4, 6], [1, 2, 0, 3, 0, 1]),  # four unpaired entries
+    ]
+    for n, rp, col in cases:
+        with pytest.raises(gl.GraphletError) as e:
+            gl.graphlet_count(dev(np.array(rp, np.int32)), dev(np.array(col, np.int32)), n)
+        assert e.value.code == -4, (rp, col)
+    torch.cuda.synchronize()
+    # a valid graph right after is unaffected
+    g = graphgen.from_edges(6, [(0, 1), (1, 2), (2, 0), (3, 4)])
+    assert gpu_counts(g, validate=False) == oracle.bruteforce(g)
 
 
 def test_explicit_workspace():
