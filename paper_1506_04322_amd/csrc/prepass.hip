@@ -104,12 +104,15 @@ __global__ void k_split_keys(const u64 *ekeys, int64_t nnz, int B, int32_t *col2
 }
 
 // lcnt[x] = |L(x)|, ucnt[x] = |U(x)|, ustart[x] = first upper position.
-// Also sums |L(x)| over all x (nnz / 2 for a symmetric CSR).
+// Also sums |L(x)| over all x (nnz / 2 for a symmetric CSR) and the entries
+// the clique pass scans: vertex v reads U(x) for every x in U(v), i.e.
+// |L(x)| |U(x)| summed over x.
 __global__ void k_split_rows(const int32_t *rp2, const int32_t *col2, int64_t n, int32_t *lcnt,
-                             int32_t *ucnt, int32_t *ustart, int32_t *max_ucnt, u64 *lower_total) {
+                             int32_t *ucnt, int32_t *ustart, int32_t *max_ucnt, u64 *lower_total,
+                             u64 *clique_entries) {
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int mx = 0;
-  u64 lsum = 0;
+  u64 lsum = 0, ce = 0;
   if (x < n) {
     const int a = rp2[x], d = rp2[x + 1] - a;
     const int l = lower_bound_dev<int32_t>(col2 + a, d, (int32_t)x);
@@ -118,11 +121,14 @@ __global__ void k_split_rows(const int32_t *rp2, const int32_t *col2, int64_t n,
     ustart[x] = a + l;
     mx = d - l;
     lsum = (u64)l;
+    ce = (u64)l * (u64)(d - l);
   }
   for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, kWave));
   lsum = wave_sum_u64(lsum);
+  ce = wave_sum_u64(ce);
   if (lane_id() == 0 && mx) atomicMax(max_ucnt, mx);
   if (lane_id() == 0 && lsum) atomicAdd(lower_total, lsum);
+  if (lane_id() == 0 && ce) atomicAdd(clique_entries, ce);
 }
 
 // tpos[p] = position of the reverse entry (x in the list of y).  Each
@@ -157,39 +163,18 @@ __global__ void k_tpos(const u64 *ekeys, const int32_t *col2, const int32_t *rp2
 
 // W[x] = wedges x - v - y with v, y below x: sum over v in L(x) of the length
 // of the prefix of N(v) below x, which ends at tpos[q] (x's own position in
-// N(v)).  Also counts the entries the clique pass scans: vertex v reads U(x)
-// for every x in U(v), i.e. |U(x)| per lower position (x, v).
-__global__ __launch_bounds__(256) void k_wedges(const u64 *ekeys, const int32_t *col2,
-                                                const int32_t *rp2, const int32_t *tpos,
-                                                const int32_t *ucnt, int64_t nnz, int B, u64 *W,
-                                                u64 *clique_entries) {
-  __shared__ u64 red[4];
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int32_t x = -1;
-  u64 len = 0, ce = 0;
-  if (p < nnz) {
-    const int32_t r = (int32_t)(ekeys[p] >> B);
-    const int32_t v = col2[p];
-    if (v < r) {
-      x = r;
-      len = (u64)(tpos[p] - rp2[v]);
-      ce = (u64)ucnt[r];
-    }
-  }
-  // one atomic per (wave, row) run for W; one per block for the entry count
-  const int32_t x0 = __shfl(x, 0, kWave);
-  if (__all(x == x0)) {
-    const u64 s = wave_sum_u64(len);
-    if (lane_id() == 0 && x0 >= 0 && s) atomicAdd(&W[x0], s);
-  } else if (x >= 0 && len) {
-    atomicAdd(&W[x], len);
-  }
-  ce = wave_sum_u64(ce);
-  if (lane_id() == 0) red[threadIdx.x / kWave] = ce;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const u64 t = red[0] + red[1] + red[2] + red[3];
-    if (t) atomicAdd(clique_entries, t);
+// N(v)).  One wave per vertex over its lower entries; one write per vertex.
+__global__ __launch_bounds__(256) void k_wedges(const int32_t *rp2, const int32_t *col2,
+                                                const int32_t *lcnt, const int32_t *tpos,
+                                                int64_t n, u64 *W) {
+  const int64_t waves = (int64_t)gridDim.x * (256 / kWave);
+  for (int64_t x = (int64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave; x < n;
+       x += waves) {
+    const int32_t a = rp2[x], l = lcnt[x];
+    u64 s = 0;
+    for (int q = a + lane_id(); q < a + l; q += kWave) s += (u64)(tpos[q] - rp2[col2[q]]);
+    s = wave_sum_u64(s);
+    if (lane_id() == 0) W[x] = s;
   }
 }
 
@@ -403,11 +388,12 @@ int run_prepass(PrepassArgs &p, Arena &a, hipStream_t s) {
   GC_TRY(radix_sort_u64(p.ekeys, p.ekeys_alt, nnz, 2 * B, &p.esorted, a, s));
   k_split_keys<<<grid1d(nnz, 256), 256, 0, s>>>(p.esorted, nnz, B, p.col2, p.tpos);
   k_split_rows<<<grid1d(n, 256), 256, 0, s>>>(p.rp2, p.col2, n, p.lcnt, p.ucnt, p.ustart,
-                                              &p.cnt->max_ucnt, &p.cnt->lower_total);
+                                              &p.cnt->max_ucnt, &p.cnt->lower_total,
+                                              &p.cnt->clique_entries);
   k_tpos<<<grid1d(nnz, 256), 256, 0, s>>>(p.esorted, p.col2, p.rp2, p.lcnt, nnz, B,
                                           &p.cnt->lower_total, p.tpos, &p.acc->err);
-  k_wedges<<<grid1d(nnz, 256), 256, 0, s>>>(p.esorted, p.col2, p.rp2, p.tpos, p.ucnt, nnz, B, p.W,
-                                            &p.cnt->clique_entries);
+  const unsigned wgrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 3) / 4, 16384));
+  k_wedges<<<wgrid, 256, 0, s>>>(p.rp2, p.col2, p.lcnt, p.tpos, n, p.W);
   k_bins<<<grid1d(n, 256), 256, 0, s>>>(p.ucnt, p.lcnt, p.W, n, p.tk[0], p.tk[1], p.tk[2],
                                         p.tk[3], p.tk[4], p.c4l, p.c4m, p.c4h, p.medium_max,
                                         p.cnt);
