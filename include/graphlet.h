@@ -334,6 +334,28 @@ int graphlet_last_timing(gc_timing *out);
  *   gc_server_stats    counters, latency percentiles over completed requests
  *                      and throughput since creation or the last reset
  *   gc_server_destroy  cancels pending requests, waits for running ones
+ *                      and frees registered graphs
+ * Resident graphs, for the localized updates of Section 6.3 served against a
+ * graph the server keeps:
+ *   gc_server_register  host CSR (copied; checked as with GC_VALIDATE), kept
+ *                      on the device with room for nnz / 8 more entries (at
+ *                      least 512 edges) until gc_server_unregister.  Returns
+ *                      the graph id > 0, which is also the id of the request
+ *                      that counts it (poll / wait give the initial counts),
+ *                      or GC_EINVAL / GC_ENOMEM as gc_server_submit.  Its
+ *                      device memory stays charged to the budget while it is
+ *                      registered.
+ *   gc_server_update   request: insert (insert = 1) or delete (0) the edge
+ *                      (u, v) of a registered graph.  Returns a request id;
+ *                      its result (poll / wait) is the graph's 17 counts after
+ *                      the change.  Updates of one graph run one at a time in
+ *                      submission order, after its registration.  A failed
+ *                      update (edge already present / absent, graph full)
+ *                      leaves the graph and its counts unchanged.
+ *   gc_server_graph_counts  1 and the current counts, 0 if the registration
+ *                      has not been counted yet, < 0 for an unknown graph
+ *   gc_server_unregister  cancels the graph's pending updates, waits for a
+ *                      running one, frees the graph
  * Calls may come from any thread.  The server owns its copies of submitted
  * graphs; it keeps no caller pointer.
  */
@@ -354,6 +376,11 @@ int gc_server_release(gc_server *s, int64_t id);
 int gc_server_stats(gc_server *s, gc_serve_stats *out);
 int gc_server_reset_stats(gc_server *s);
 void gc_server_destroy(gc_server *s);
+int64_t gc_server_register(gc_server *s, int64_t n, int64_t nnz, const int32_t *row_ptr,
+                           const int32_t *col);
+int64_t gc_server_update(gc_server *s, int64_t graph, int32_t u, int32_t v, int insert);
+int gc_server_graph_counts(gc_server *s, int64_t graph, gc_u128 out_counts[17]);
+int gc_server_unregister(gc_server *s, int64_t graph);
 const char *gc_server_last_error(void);
 
 /* Message of the calling thread's most recent error ("" if none). */

@@ -75,6 +75,10 @@ EXPORTS = [
     "graphlet_last_timing",
     "gc_server_create",
     "gc_server_submit",
+    "gc_server_register",
+    "gc_server_update",
+    "gc_server_graph_counts",
+    "gc_server_unregister",
     "gc_server_poll",
     "gc_server_wait",
     "gc_server_cancel",
@@ -162,6 +166,15 @@ def load():
     lib.gc_server_create.restype = ctypes.c_void_p
     lib.gc_server_submit.argtypes = [P, ctypes.c_int64, ctypes.c_int64, P, P]
     lib.gc_server_submit.restype = ctypes.c_int64
+    lib.gc_server_register.argtypes = [P, ctypes.c_int64, ctypes.c_int64, P, P]
+    lib.gc_server_register.restype = ctypes.c_int64
+    lib.gc_server_update.argtypes = [P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int]
+    lib.gc_server_update.restype = ctypes.c_int64
+    lib.gc_server_graph_counts.argtypes = [P, ctypes.c_int64, ctypes.POINTER(_U128)]
+    lib.gc_server_graph_counts.restype = ctypes.c_int
+    lib.gc_server_unregister.argtypes = [P, ctypes.c_int64]
+    lib.gc_server_unregister.restype = ctypes.c_int
     for f in (lib.gc_server_poll, lib.gc_server_wait):
         f.argtypes = [P, ctypes.c_int64, ctypes.POINTER(_U128), ctypes.POINTER(ctypes.c_double)]
         f.restype = ctypes.c_int
@@ -485,6 +498,43 @@ class Server:
         if rid < 0:
             raise GraphletError(int(rid), self._lib.gc_server_last_error().decode())
         return int(rid)
+
+    def register(self, n: int, row_ptr, col) -> int:
+        """Keeps the graph resident for edge updates; returns its id (also a
+        request id: wait() on it gives the initial counts)."""
+        import numpy as np
+
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        c = np.ascontiguousarray(col, dtype=np.int32)
+        gid = self._lib.gc_server_register(self._h, int(n), int(c.shape[0]), rp.ctypes.data,
+                                           c.ctypes.data if c.shape[0] else None)
+        if gid < 0:
+            raise GraphletError(int(gid), self._lib.gc_server_last_error().decode())
+        return int(gid)
+
+    def update(self, graph: int, u: int, v: int, insert: bool) -> int:
+        """Queues an edge insertion or deletion on a registered graph; the
+        request's result is the graph's counts after it."""
+        rid = self._lib.gc_server_update(self._h, int(graph), int(u), int(v), 1 if insert else 0)
+        if rid < 0:
+            raise GraphletError(int(rid), self._lib.gc_server_last_error().decode())
+        return int(rid)
+
+    def graph_counts(self, graph: int):
+        """Current counts of a registered graph, or None before its
+        registration has been counted."""
+        out = (_U128 * 17)()
+        rc = self._lib.gc_server_graph_counts(self._h, int(graph), out)
+        if rc < 0:
+            raise GraphletError(rc, self._lib.gc_server_last_error().decode())
+        if rc == 0:
+            return None
+        return [int(o.lo) | (int(o.hi) << 64) for o in out]
+
+    def unregister(self, graph: int) -> None:
+        rc = self._lib.gc_server_unregister(self._h, int(graph))
+        if rc < 0:
+            raise GraphletError(rc, self._lib.gc_server_last_error().decode())
 
     def _result(self, fn, rid):
         out = (_U128 * 17)()

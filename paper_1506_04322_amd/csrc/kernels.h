@@ -193,7 +193,7 @@ struct C4Args {
 constexpr int kDenseSlab = 128;        // hubs per slab: two mask words per vertex
 constexpr int kDenseHubMax = 8192;     // candidates examined by the host
 constexpr int kDenseShortDeg = 1023;   // rows up to this degree: one thread, 10 bit planes
-constexpr double kDenseSlabPs = 1.2e9;      // measured cost of one slab pass (R-MAT s22)
+constexpr double kDenseSlabPs = 1.6e9;      // measured cost of one slab pass (R-MAT s22)
 constexpr double kSparseWedgePs = 4.9;      // measured cost of one heavy wedge by work items
 struct HubArgs {
   const int32_t *rp2, *col2, *lcnt;

@@ -11,6 +11,14 @@
 // Each request's CSR stays resident on the device from admission until its
 // counts are on the host; each request runs the same graphlet_count path as
 // a standalone call, so its result does not depend on what else is running.
+//
+// Resident graphs: a registered graph keeps its CSR (two buffers, the live
+// one and a spare) and its counts on the device until it is unregistered.
+// Edge updates against it are requests too; those of one graph run one at a
+// time in submission order.  Each takes the localized update of the counts
+// (graphlet_update_edge on the live CSR), then writes the changed CSR into
+// the spare buffer and swaps; a failed update leaves graph and counts as
+// they were.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,6 +37,8 @@
 
 namespace gc {
 size_t workspace_bound(int64_t n, int64_t nnz, int max_deg, int max_ucnt, bool per_edge);
+int csr_apply_edge(const gc_csr *g, int32_t u, int32_t v, int insert, int32_t *rp_out,
+                   int32_t *col_out, hipStream_t s);
 }
 
 namespace {
@@ -36,9 +46,27 @@ namespace {
 using Clock = std::chrono::steady_clock;
 
 enum State { PENDING = 0, RUNNING = 1, DONE = 2, FAILED = 3, CANCELLED = 4 };
+enum Kind { COUNT = 0, REGISTER = 1, UPDATE = 2 };
+
+// A registered graph.  Its id is the id of its registration request.
+struct Resident {
+  int64_t id = 0;
+  int64_t n = 0, nnz = 0, cap = 0;  // cap: entries each col buffer holds
+  int32_t *rp[2] = {nullptr, nullptr}, *col[2] = {nullptr, nullptr};
+  int live = 0;
+  bool ready = false;  // registration counted
+  bool busy = false;   // a request on it is running
+  bool gone = false;   // registration failed or unregistered
+  size_t bytes = 0;    // device memory held while registered
+  gc_u128 counts[17];
+};
 
 struct Request {
   int64_t id = 0;
+  Kind kind = COUNT;
+  Resident *g = nullptr;  // REGISTER, UPDATE
+  int32_t u = 0, v = 0;
+  int insert = 0;
   int64_t n = 0, nnz = 0;
   std::vector<int32_t> rp, col;
   size_t footprint = 0;
@@ -63,6 +91,7 @@ struct gc_server {
   std::condition_variable cv_work, cv_done;
   std::deque<Request *> pending;
   std::unordered_map<int64_t, Request *> all;
+  std::unordered_map<int64_t, Resident *> graphs;
   std::vector<std::thread> workers;
   int64_t next_id = 1;
   bool stop = false;
@@ -79,6 +108,135 @@ namespace {
 
 thread_local std::string t_srv_err;
 
+// Completion of a request under the lock: state, statistics, wake-ups.
+// `keep` bytes of its footprint stay charged (a registered graph's CSR).
+void finish(gc_server *S, Request *r, int rc, const std::string &err, size_t keep) {
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->in_use -= r->footprint - keep;
+    S->running--;
+    r->t_done = Clock::now();
+    r->rc = rc;
+    r->err = err;
+    r->rp.clear();
+    r->rp.shrink_to_fit();
+    r->col.clear();
+    r->col.shrink_to_fit();
+    if (r->g) r->g->busy = false;
+    if (r->cancel) {
+      r->state = CANCELLED;
+      S->cancelled++;
+    } else if (rc == GC_OK) {
+      r->state = DONE;
+      S->completed++;
+      if (r->kind != UPDATE) S->edges_done += r->nnz / 2;
+      S->latencies.push_back(
+          std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count());
+      S->t_last = r->t_done;
+    } else {
+      r->state = FAILED;
+      S->failed++;
+    }
+  }
+  S->cv_done.notify_all();
+  S->cv_work.notify_all();
+}
+
+void free_resident(Resident *G) {
+  for (int b = 0; b < 2; b++) {
+    if (G->rp[b]) (void)hipFree(G->rp[b]);
+    if (G->col[b]) (void)hipFree(G->col[b]);
+    G->rp[b] = nullptr;
+    G->col[b] = nullptr;
+  }
+}
+
+// Registration: both CSR buffers are allocated for the graph's lifetime, the
+// CSR is uploaded into one and counted.  On failure the graph is dropped and
+// its pending updates fail.
+void run_register(gc_server *S, Request *r, hipStream_t st) {
+  Resident *G = r->g;
+  int rc = GC_OK;
+  std::string err;
+  hipError_t e = hipSuccess;
+  for (int b = 0; b < 2 && e == hipSuccess; b++) {
+    e = hipMalloc((void **)&G->rp[b], sizeof(int32_t) * (size_t)(G->n + 1));
+    if (e == hipSuccess) e = hipMalloc((void **)&G->col[b], sizeof(int32_t) * (size_t)G->cap);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(G->rp[0], r->rp.data(), sizeof(int32_t) * (size_t)(G->n + 1),
+                       hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && G->nnz > 0)
+    e = hipMemcpyAsync(G->col[0], r->col.data(), sizeof(int32_t) * (size_t)G->nnz,
+                       hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) {
+    rc = e == hipErrorOutOfMemory ? GC_ENOMEM : GC_EHIP;
+    err = hipGetErrorString(e);
+  } else {
+    gc_csr g{G->n, G->nnz, G->rp[0], G->col[0]};
+    rc = graphlet_count(&g, r->out, nullptr, nullptr, 0, st, S->flags | GC_VALIDATE);
+    if (rc != GC_OK) err = graphlet_last_error();
+  }
+  (void)hipStreamSynchronize(st);
+  if (rc == GC_OK) {
+    std::lock_guard<std::mutex> lk(S->mu);
+    std::memcpy(G->counts, r->out, sizeof(G->counts));
+    G->live = 0;
+    G->ready = true;
+  } else {
+    free_resident(G);
+    std::lock_guard<std::mutex> lk(S->mu);
+    G->gone = true;
+    for (auto it = S->pending.begin(); it != S->pending.end();) {
+      if ((*it)->g == G) {
+        (*it)->state = FAILED;
+        (*it)->rc = GC_EINVAL;
+        (*it)->err = "the graph's registration failed";
+        (*it)->g = nullptr;
+        S->failed++;
+        it = S->pending.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  finish(S, r, rc, err, rc == GC_OK ? G->bytes : 0);
+}
+
+// One edge update of a registered graph: the counts by the localized update
+// on the live CSR, then the changed CSR into the spare buffer; both are
+// committed together.
+void run_update(gc_server *S, Request *r, hipStream_t st) {
+  Resident *G = r->g;
+  gc_csr cur{G->n, G->nnz, G->rp[G->live], G->col[G->live]};
+  gc_u128 c[17];
+  std::memcpy(c, G->counts, sizeof(c));
+  std::string err;
+  int rc = graphlet_update_edge(&cur, r->u, r->v, r->insert, c, st);
+  if (rc != GC_OK) {
+    err = graphlet_last_error();
+  } else if (r->insert && G->nnz + 2 > G->cap) {
+    rc = GC_ENOMEM;
+    err = "the registered graph has no room for more edges";
+  } else {
+    const int spare = 1 - G->live;
+    rc = gc::csr_apply_edge(&cur, r->u, r->v, r->insert, G->rp[spare], G->col[spare], st);
+    if (rc != GC_OK) err = graphlet_last_error();
+    if (hipStreamSynchronize(st) != hipSuccess && rc == GC_OK) {
+      rc = GC_EHIP;
+      err = "stream error after the CSR update";
+    }
+  }
+  if (rc == GC_OK) {
+    std::lock_guard<std::mutex> lk(S->mu);
+    G->live = 1 - G->live;
+    G->nnz += r->insert ? 2 : -2;
+    std::memcpy(G->counts, c, sizeof(c));
+    std::memcpy(r->out, c, sizeof(c));
+  }
+  finish(S, r, rc, err, 0);
+}
+
 void worker_main(gc_server *S) {
   (void)hipSetDevice(S->device);
   hipStream_t st = nullptr;
@@ -89,10 +247,14 @@ void worker_main(gc_server *S) {
       std::unique_lock<std::mutex> lk(S->mu);
       while (true) {
         if (S->stop) break;
-        // first pending request, in order, that fits the remaining budget
+        // first pending request, in order, that fits the remaining budget;
+        // an update waits for its graph's registration and for the update
+        // before it (the graph is busy meanwhile)
         for (auto it = S->pending.begin(); it != S->pending.end(); ++it) {
-          if (S->in_use + (*it)->footprint <= S->budget) {
-            r = *it;
+          Request *q = *it;
+          if (q->kind == UPDATE && (!q->g->ready || q->g->busy)) continue;
+          if (S->in_use + q->footprint <= S->budget) {
+            r = q;
             S->pending.erase(it);
             break;
           }
@@ -106,6 +268,15 @@ void worker_main(gc_server *S) {
       S->running++;
       r->state = RUNNING;
       r->t_start = Clock::now();
+      if (r->g) r->g->busy = true;
+    }
+    if (r->kind == REGISTER) {
+      run_register(S, r, st);
+      continue;
+    }
+    if (r->kind == UPDATE) {
+      run_update(S, r, st);
+      continue;
     }
     // run outside the lock
     int rc = GC_OK;
@@ -130,34 +301,7 @@ void worker_main(gc_server *S) {
     if (d_col) (void)hipFreeAsync(d_col, st);
     if (d_rp) (void)hipFreeAsync(d_rp, st);
     (void)hipStreamSynchronize(st);
-    {
-      std::lock_guard<std::mutex> lk(S->mu);
-      S->in_use -= r->footprint;
-      S->running--;
-      r->t_done = Clock::now();
-      r->rc = rc;
-      r->err = err;
-      r->rp.clear();
-      r->rp.shrink_to_fit();
-      r->col.clear();
-      r->col.shrink_to_fit();
-      if (r->cancel) {
-        r->state = CANCELLED;
-        S->cancelled++;
-      } else if (rc == GC_OK) {
-        r->state = DONE;
-        S->completed++;
-        S->edges_done += r->nnz / 2;
-        S->latencies.push_back(
-            std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count());
-        S->t_last = r->t_done;
-      } else {
-        r->state = FAILED;
-        S->failed++;
-      }
-    }
-    S->cv_done.notify_all();
-    S->cv_work.notify_all();
+    finish(S, r, rc, err, 0);
   }
   if (st) (void)hipStreamDestroy(st);
 }
@@ -403,6 +547,153 @@ int gc_server_reset_stats(gc_server *S) {
   return GC_OK;
 }
 
+int64_t gc_server_register(gc_server *S, int64_t n, int64_t nnz, const int32_t *row_ptr,
+                           const int32_t *col) {
+  t_srv_err.clear();
+  if (!S || n <= 0 || nnz < 0 || (nnz & 1) || n > 2147483646LL || nnz > 2147483646LL ||
+      !row_ptr || (nnz > 0 && !col) || row_ptr[0] != 0 || row_ptr[n] != nnz) {
+    t_srv_err = "invalid graph arguments";
+    return GC_EINVAL;
+  }
+  int max_deg = 0, max_ucnt = 0;
+  if (!host_maxima(n, row_ptr, col, &max_deg, &max_ucnt)) {
+    t_srv_err = "malformed CSR (row offsets or vertex ids)";
+    return GC_EINVAL;
+  }
+  Resident *G = new (std::nothrow) Resident();
+  Request *r = new (std::nothrow) Request();
+  if (!G || !r) {
+    delete G;
+    delete r;
+    return GC_ENOMEM;
+  }
+  G->n = n;
+  G->nnz = nnz;
+  // room for nnz / 8 more entries (at least 512 edges) before the graph is full
+  G->cap = nnz + std::max<int64_t>(1024, (nnz / 8 + 1) & ~int64_t(1));
+  if (G->cap > 2147483646LL) G->cap = 2147483646LL & ~int64_t(1);
+  G->bytes = 2 * sizeof(int32_t) * (size_t)(n + 1 + G->cap);
+  const size_t fp =
+      G->bytes + gc::workspace_bound(n, nnz, max_deg, max_ucnt, false) + (1u << 20);
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (fp > S->budget) {
+    delete G;
+    delete r;
+    t_srv_err = "graph footprint exceeds the server's device-memory budget";
+    S->rejected++;
+    return GC_ENOMEM;
+  }
+  r->id = S->next_id++;
+  r->kind = REGISTER;
+  r->g = G;
+  G->id = r->id;
+  r->n = n;
+  r->nnz = nnz;
+  r->rp.assign(row_ptr, row_ptr + n + 1);
+  if (nnz) r->col.assign(col, col + nnz);
+  r->footprint = fp;
+  r->t_submit = Clock::now();
+  if (!S->any) {
+    S->t_first = r->t_submit;
+    S->any = true;
+  }
+  S->all[r->id] = r;
+  S->graphs[G->id] = G;
+  S->pending.push_back(r);
+  S->submitted++;
+  S->cv_work.notify_one();
+  return G->id;
+}
+
+int64_t gc_server_update(gc_server *S, int64_t graph, int32_t u, int32_t v, int insert) {
+  t_srv_err.clear();
+  if (!S) return GC_EINVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->graphs.find(graph);
+  if (it == S->graphs.end() || it->second->gone) {
+    t_srv_err = "unknown graph";
+    S->rejected++;
+    return GC_EINVAL;
+  }
+  Resident *G = it->second;
+  if (u < 0 || v < 0 || u >= G->n || v >= G->n || u == v) {
+    t_srv_err = "endpoint out of range, or u == v";
+    S->rejected++;
+    return GC_EINVAL;
+  }
+  Request *r = new (std::nothrow) Request();
+  if (!r) return GC_ENOMEM;
+  r->id = S->next_id++;
+  r->kind = UPDATE;
+  r->g = G;
+  r->u = u;
+  r->v = v;
+  r->insert = insert ? 1 : 0;
+  // the two membership bitmaps and the accumulators of the update
+  r->footprint = 2 * sizeof(uint32_t) * (size_t)((G->n + 31) / 32) + (1u << 16);
+  r->t_submit = Clock::now();
+  if (!S->any) {
+    S->t_first = r->t_submit;
+    S->any = true;
+  }
+  S->all[r->id] = r;
+  S->pending.push_back(r);
+  S->submitted++;
+  S->cv_work.notify_one();
+  return r->id;
+}
+
+int gc_server_graph_counts(gc_server *S, int64_t graph, gc_u128 out_counts[17]) {
+  t_srv_err.clear();
+  if (!S || !out_counts) return GC_EINVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->graphs.find(graph);
+  if (it == S->graphs.end() || it->second->gone) {
+    t_srv_err = "unknown graph";
+    return GC_EINVAL;
+  }
+  if (!it->second->ready) return 0;
+  std::memcpy(out_counts, it->second->counts, sizeof(it->second->counts));
+  return 1;
+}
+
+int gc_server_unregister(gc_server *S, int64_t graph) {
+  t_srv_err.clear();
+  if (!S) return GC_EINVAL;
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->graphs.find(graph);
+  if (it == S->graphs.end()) {
+    t_srv_err = "unknown graph";
+    return GC_EINVAL;
+  }
+  Resident *G = it->second;
+  // pending requests on the graph are cancelled; a running one finishes
+  for (auto p = S->pending.begin(); p != S->pending.end();) {
+    if ((*p)->g == G) {
+      (*p)->state = CANCELLED;
+      (*p)->g = nullptr;
+      (*p)->rp.clear();
+      (*p)->col.clear();
+      S->cancelled++;
+      p = S->pending.erase(p);
+    } else {
+      ++p;
+    }
+  }
+  S->cv_done.wait(lk, [&] { return !G->busy; });
+  for (auto &kv : S->all)
+    if (kv.second->g == G) kv.second->g = nullptr;
+  if (G->ready && !G->gone) S->in_use -= G->bytes;
+  S->graphs.erase(G->id);
+  lk.unlock();
+  (void)hipSetDevice(S->device);
+  free_resident(G);
+  delete G;
+  S->cv_done.notify_all();
+  S->cv_work.notify_all();
+  return GC_OK;
+}
+
 void gc_server_destroy(gc_server *S) {
   if (!S) return;
   {
@@ -416,6 +707,11 @@ void gc_server_destroy(gc_server *S) {
   S->cv_work.notify_all();
   for (auto &t : S->workers) t.join();
   for (auto &kv : S->all) delete kv.second;
+  (void)hipSetDevice(S->device);
+  for (auto &kv : S->graphs) {
+    free_resident(kv.second);
+    delete kv.second;
+  }
   delete S;
 }
 

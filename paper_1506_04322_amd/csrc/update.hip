@@ -94,6 +94,23 @@ __global__ __launch_bounds__(256) void k_two_hop(const int32_t *rp, const int32_
       if (a[i]) atomicAdd(&acc[i], a[i]);
 }
 
+// Row offsets after inserting (sign 1) or deleting (sign -1) the edge
+// (a, b), a < b: rows after a gain or lose one entry, rows after b two.
+__global__ void k_shift_rows(const int32_t *rp, int64_t n, int32_t a, int32_t b, int sign,
+                             int32_t *rp_out) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x > n) return;
+  rp_out[x] = rp[x] + sign * ((x > a) + (x > b));
+}
+
+// The two new entries of an insertion.
+__global__ void k_put2(int32_t *col, int64_t i1, int32_t v1, int64_t i2, int32_t v2) {
+  if (threadIdx.x == 0) {
+    col[i1] = v1;
+    col[i2] = v2;
+  }
+}
+
 __global__ void k_zero(u64 *p, int n) {
   if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
 }
@@ -266,6 +283,66 @@ int update_edge(const gc_csr *g, int32_t u, int32_t v, int insert, gc_u128 count
 }
 
 }  // namespace
+
+// Writes the CSR of g with the edge (u, v) inserted (insert = 1) or deleted
+// into rp_out (n + 1 entries) and col_out (nnz + 2 resp. nnz - 2 entries),
+// which must not overlap g's arrays.  Rows stay sorted: the entry goes to
+// its place in N(u) and N(v), found on host copies of the two rows.  The
+// edge must be absent (insert) or present (delete), else GC_EINVAL.
+int csr_apply_edge(const gc_csr *g, int32_t u, int32_t v, int insert, int32_t *rp_out,
+                   int32_t *col_out, hipStream_t s) {
+  if (!g || !rp_out || !col_out || u < 0 || v < 0 || u >= g->n || v >= g->n || u == v) {
+    set_error("invalid arguments");
+    return GC_EINVAL;
+  }
+  const int32_t a = std::min(u, v), b = std::max(u, v);
+  int32_t ra[2], rb[2];
+  GC_TRY_HIP(hipMemcpyAsync(ra, g->row_ptr + a, 8, hipMemcpyDeviceToHost, s));
+  GC_TRY_HIP(hipMemcpyAsync(rb, g->row_ptr + b, 8, hipMemcpyDeviceToHost, s));
+  GC_TRY_HIP(hipStreamSynchronize(s));
+  std::vector<int32_t> la((size_t)(ra[1] - ra[0])), lb((size_t)(rb[1] - rb[0]));
+  if (!la.empty())
+    GC_TRY_HIP(hipMemcpyAsync(la.data(), g->col + ra[0], 4 * la.size(), hipMemcpyDeviceToHost, s));
+  if (!lb.empty())
+    GC_TRY_HIP(hipMemcpyAsync(lb.data(), g->col + rb[0], 4 * lb.size(), hipMemcpyDeviceToHost, s));
+  GC_TRY_HIP(hipStreamSynchronize(s));
+  // pa: position of b in row a (or where it would go), pb: of a in row b
+  const int64_t ia = std::lower_bound(la.begin(), la.end(), b) - la.begin();
+  const int64_t ib = std::lower_bound(lb.begin(), lb.end(), a) - lb.begin();
+  const bool has = ia < (int64_t)la.size() && la[ia] == b;
+  const bool has_b = ib < (int64_t)lb.size() && lb[ib] == a;
+  if (has != has_b) {
+    set_error("CSR is not symmetric at (%d, %d)", a, b);
+    return GC_EASYMMETRIC;
+  }
+  if (insert == has) {
+    set_error(insert ? "edge (%d, %d) is already in the graph" : "edge (%d, %d) is not in the graph",
+              u, v);
+    return GC_EINVAL;
+  }
+  const int64_t pa = ra[0] + ia, pb = rb[0] + ib, nnz = g->nnz;  // pa < pb
+  auto copy = [&](int64_t dst, int64_t src, int64_t len) -> hipError_t {
+    if (len <= 0) return hipSuccess;
+    return hipMemcpyAsync(col_out + dst, g->col + src, 4 * (size_t)len, hipMemcpyDeviceToDevice,
+                          s);
+  };
+  if (insert) {
+    GC_TRY_HIP(copy(0, 0, pa));
+    GC_TRY_HIP(copy(pa + 1, pa, pb - pa));
+    GC_TRY_HIP(copy(pb + 2, pb, nnz - pb));
+    k_put2<<<1, 64, 0, s>>>(col_out, pa, b, pb + 1, a);
+  } else {
+    GC_TRY_HIP(copy(0, 0, pa));
+    GC_TRY_HIP(copy(pa, pa + 1, pb - pa - 1));
+    GC_TRY_HIP(copy(pb - 1, pb + 1, nnz - pb - 1));
+  }
+  GC_TRY_HIP(hipGetLastError());
+  k_shift_rows<<<grid1d(g->n + 1, 256), 256, 0, s>>>(g->row_ptr, g->n, a, b, insert ? 1 : -1,
+                                                      rp_out);
+  GC_TRY_HIP(hipGetLastError());
+  return GC_OK;
+}
+
 }  // namespace gc
 
 extern "C" int graphlet_update_edge(const gc_csr *g, int32_t u, int32_t v, int insert,

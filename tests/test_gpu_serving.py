@@ -100,3 +100,121 @@ def test_cancel_pending_request():
             srv.wait(ids[-1])
         st = srv.stats()
     assert st["cancelled"] >= 1 and st["completed"] == len(graphs) - 1
+
+
+# ------------------------------------------------------------ resident graphs
+
+
+def _edge_set(g):
+    eu, ev = oracle.edges(g)
+    return set(zip(eu.tolist(), ev.tolist()))
+
+
+def test_resident_graph_update_chain_vs_oracle():
+    # a chain of insertions and deletions against a graph the server keeps:
+    # every result equals the oracle's counts of the changed graph
+    rng = np.random.default_rng(404)
+    n = 36
+    iu = np.triu_indices(n, 1)
+    mask = rng.random(len(iu[0])) < 0.25
+    edges = set(zip(iu[0][mask].tolist(), iu[1][mask].tolist()))
+    g = graphgen.from_edges(n, sorted(edges))
+    with gl.Server(budget_bytes=4 << 30, slots=3) as srv:
+        gid = srv.register(g.n, g.row_ptr, g.col)
+        counts, _ = srv.wait(gid)
+        assert counts == oracle.bruteforce(g)
+        rids, wants = [], []
+        for _ in range(30):
+            a, b = sorted(int(x) for x in rng.choice(n, 2, replace=False))
+            insert = (a, b) not in edges
+            edges.symmetric_difference_update({(a, b)})
+            rids.append(srv.update(gid, a, b, insert))
+            wants.append(oracle.bruteforce(graphgen.from_edges(n, sorted(edges))))
+        for rid, want in zip(rids, wants):
+            assert srv.wait(rid)[0] == want
+        assert srv.graph_counts(gid) == wants[-1]
+        # the kept CSR is the changed graph: a plain request on it agrees
+        final = graphgen.from_edges(n, sorted(edges))
+        assert srv.wait(srv.submit(final.n, final.row_ptr, final.col))[0] == wants[-1]
+        srv.unregister(gid)
+        with pytest.raises(gl.GraphletError):
+            srv.update(gid, 0, 1, True)
+
+
+def test_resident_graphs_interleaved_with_requests():
+    # two resident graphs (one skewed, with hubs) updated in an interleaved
+    # stream beside plain requests; each graph's updates apply in order
+    rng = np.random.default_rng(505)
+    gs = [graphgen.chung_lu(3000, 2.1, 3.0, 20000, 12), graphgen.rmat(11, 8, 0.57, 0.19, 0.19, 4)]
+    sets = [_edge_set(g) for g in gs]
+    plain = [graphgen.from_edges(50, [(i, (i * 7 + 3) % 50) for i in range(50) if i != (i * 7 + 3) % 50])]
+    with gl.Server(budget_bytes=16 << 30, slots=4) as srv:
+        gids = [srv.register(g.n, g.row_ptr, g.col) for g in gs]
+        chains = [[], []]
+        deg = [np.diff(g.row_ptr) for g in gs]
+        for step in range(24):
+            k = step % 2
+            g, es = gs[k], sets[k]
+            if step % 3 == 0:  # an edge at the highest-degree vertex
+                hub = int(np.argmax(deg[k]))
+                other = int(rng.integers(g.n))
+                if other == hub:
+                    other = (hub + 1) % g.n
+                a, b = min(hub, other), max(hub, other)
+            else:
+                a, b = sorted(int(x) for x in rng.choice(g.n, 2, replace=False))
+            insert = (a, b) not in es
+            es.symmetric_difference_update({(a, b)})
+            chains[k].append(srv.update(gids[k], a, b, insert))
+            if step % 6 == 0:
+                srv.submit(plain[0].n, plain[0].row_ptr, plain[0].col)
+        for k in range(2):
+            last = [srv.wait(r)[0] for r in chains[k]][-1]
+            final = graphgen.from_edges(gs[k].n, sorted(sets[k]))
+            assert last == oracle.identity_route(final)
+            assert srv.graph_counts(gids[k]) == last
+        for gid in gids:
+            srv.unregister(gid)
+        assert srv.stats()["failed"] == 0
+
+
+def test_resident_graph_failed_updates_leave_it_unchanged():
+    g = graphgen.from_edges(30, [(0, 1), (1, 2), (2, 0), (3, 4)])
+    with gl.Server(budget_bytes=2 << 30, slots=2) as srv:
+        gid = srv.register(g.n, g.row_ptr, g.col)
+        base, _ = srv.wait(gid)
+        bad = srv.update(gid, 5, 6, False)  # not an edge
+        dup = srv.update(gid, 0, 1, True)   # already an edge
+        ok = srv.update(gid, 3, 4, False)
+        with pytest.raises(gl.GraphletError):
+            srv.wait(bad)
+        with pytest.raises(gl.GraphletError):
+            srv.wait(dup)
+        after = srv.wait(ok)[0]
+        assert after == oracle.bruteforce(graphgen.from_edges(30, [(0, 1), (1, 2), (2, 0)]))
+        assert srv.graph_counts(gid) == after
+        with pytest.raises(gl.GraphletError):
+            srv.update(gid, 0, 30, True)  # endpoint out of range
+        with pytest.raises(gl.GraphletError):
+            srv.update(gid + 1000, 0, 1, True)  # unknown graph
+        srv.unregister(gid)
+    assert base == oracle.bruteforce(g)
+
+
+def test_resident_graph_room_runs_out():
+    # an empty graph has room for 512 edges; the next insertion fails and the
+    # graph keeps its counts
+    n = 40
+    g = graphgen.from_edges(n, [])
+    pairs = [(a, b) for a in range(n) for b in range(a + 1, n)][:513]
+    with gl.Server(budget_bytes=2 << 30, slots=1) as srv:
+        gid = srv.register(g.n, g.row_ptr, g.col)
+        srv.wait(gid)
+        rids = [srv.update(gid, a, b, True) for a, b in pairs]
+        for rid in rids[:-1]:
+            srv.wait(rid)
+        with pytest.raises(gl.GraphletError) as e:
+            srv.wait(rids[-1])
+        assert e.value.code == -6
+        assert srv.graph_counts(gid) == oracle.bruteforce(graphgen.from_edges(n, pairs[:-1]))
+        srv.unregister(gid)
