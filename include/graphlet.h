@@ -355,7 +355,10 @@ int graphlet_last_timing(gc_timing *out);
  *   gc_server_graph_counts  1 and the current counts, 0 if the registration
  *                      has not been counted yet, < 0 for an unknown graph
  *   gc_server_unregister  cancels the graph's pending updates, waits for a
- *                      running one, frees the graph
+ *                      running one, frees the graph.  Cancelling a pending
+ *                      registration (gc_server_cancel on the graph id) also
+ *                      cancels the graph's queued updates and refuses new
+ *                      ones; a running registration completes.
  * Calls may come from any thread.  The server owns its copies of submitted
  * graphs; it keeps no caller pointer.
  */

@@ -491,6 +491,23 @@ int gc_server_cancel(gc_server *S, int64_t id) {
     r->rp.clear();
     r->col.clear();
     S->cancelled++;
+    if (r->kind == REGISTER) {
+      // the graph never becomes resident: its queued updates are cancelled
+      // too (it stays known until gc_server_unregister, holding no memory)
+      Resident *G = r->g;
+      G->gone = true;
+      for (auto p = S->pending.begin(); p != S->pending.end();) {
+        if ((*p)->g == G) {
+          (*p)->state = CANCELLED;
+          (*p)->g = nullptr;
+          S->cancelled++;
+          p = S->pending.erase(p);
+        } else {
+          ++p;
+        }
+      }
+      r->g = nullptr;
+    }
     S->cv_done.notify_all();
   } else if (r->state == RUNNING) {
     r->cancel = true;  // result discarded when the device work ends

@@ -218,3 +218,23 @@ def test_resident_graph_room_runs_out():
         assert e.value.code == -6
         assert srv.graph_counts(gid) == oracle.bruteforce(graphgen.from_edges(n, pairs[:-1]))
         srv.unregister(gid)
+
+
+def test_cancelled_registration_cancels_its_updates():
+    # one slot kept busy by a large request, so the registration is still
+    # pending when it is cancelled
+    big = C.serve_graph("cl", 200_000, 1_000_000, 9)
+    g = graphgen.from_edges(20, [(0, 1), (1, 2)])
+    with gl.Server(budget_bytes=8 << 30, slots=1) as srv:
+        busy = srv.submit(big.n, big.row_ptr, big.col)
+        gid = srv.register(g.n, g.row_ptr, g.col)
+        upd = srv.update(gid, 2, 3, True)
+        srv.cancel(gid)
+        for rid in (gid, upd):
+            with pytest.raises(gl.GraphletError):
+                srv.wait(rid)
+        with pytest.raises(gl.GraphletError):
+            srv.update(gid, 3, 4, True)
+        srv.wait(busy)
+        srv.unregister(gid)
+        assert srv.stats()["cancelled"] >= 2
