@@ -64,10 +64,10 @@ TRAFFIC_SOURCES = ["paper_1506_04322_amd/csrc/cycles.hip", "paper_1506_04322_amd
                    "paper_1506_04322_amd/csrc/common.h"]
 
 
-def measured_traffic(kernel: str, workload: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 byte
-    counters, or None when they were taken on other sources or another
-    workload."""
+def measured_traffic(kernel: str, workload: str, field: str = "traffic_bytes_per_launch"):
+    """HBM bytes per launch of `kernel` (or another recorded field, such as
+    its L2 hit rate) from the committed rocprofv3 counters, or None when they
+    were taken on other sources or another workload."""
     if workload != "rmat22" or not os.path.exists(TRAFFIC_PROFILE):
         return None
     fields = {}
@@ -81,9 +81,9 @@ def measured_traffic(kernel: str, workload: str):
     for rel in TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
-    if h.hexdigest() != fields.get("source_sha256"):
+    if h.hexdigest() != fields.get("source_sha256") or field not in fields:
         return None
-    return float(fields["traffic_bytes_per_launch"])
+    return float(fields[field])
 
 
 def roofline_from_timing(t: dict, per_edge: bool = False):
@@ -114,8 +114,12 @@ def run_single(args, torch, gl):
     g = build()
     log(f"[bench] generated {args.workload}: n={g.n} m={g.m} in {time.time() - t0:.1f}s")
     dev = torch.device("cuda:0")
+    torch.cuda.synchronize()
+    t_up = time.perf_counter()
     rp = torch.from_numpy(g.row_ptr).to(dev)
     col = torch.from_numpy(g.col).to(dev)
+    torch.cuda.synchronize()
+    h2d_ms = (time.perf_counter() - t_up) * 1e3  # pageable host CSR -> HBM, not in value
     ws_bytes = gl.graphlet_workspace_size(rp, col, g.n, per_edge=per_edge)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     pe = torch.empty((3, max(g.m, 1)), dtype=torch.int64, device=dev) if per_edge else None
@@ -134,9 +138,12 @@ def run_single(args, torch, gl):
         log(f"[bench] warmup {i} done")
     torch.cuda.synchronize()
     phase_sum = {}
+    step_ms = []
     t0 = time.perf_counter()
     for i in range(args.steps):
-        c = call()
+        ts = time.perf_counter()
+        c = call()  # returns with the counts on the host
+        step_ms.append((time.perf_counter() - ts) * 1e3)
         t = gl.graphlet_last_timing()
         for k, v in t.items():
             phase_sum[k] = phase_sum.get(k, 0) + v
@@ -150,6 +157,7 @@ def run_single(args, torch, gl):
     log("[bench] phases: " + ", ".join(f"{k}={v:.3f}" for k, v in timing.items() if k.endswith("_ms")))
     name, roof = roofline_from_timing(timing, per_edge)
     roof["traffic"] = measured_traffic(roof["kernel"], args.workload)
+    roof["l2_hit_rate"] = measured_traffic(roof["kernel"], args.workload, "l2_hit_rate")
     value = g.m / (ms / 1e3)
     res = {
         "metric": "edges/sec full k<=4 graphlet counts",
@@ -169,6 +177,10 @@ def run_single(args, torch, gl):
                    "output": "17 x u128 global counts" + (
                        " + 3 x int64[m] per-edge arrays" if per_edge else "")},
         "roofline": roof,
+        "step_ms": {"min": min(step_ms), "median": sorted(step_ms)[len(step_ms) // 2],
+                    "max": max(step_ms)},
+        "h2d_ms": h2d_ms,
+        "edges_per_s_incl_h2d": g.m / ((ms + h2d_ms) / 1e3),
         "phases_ms": {k: round(v, 3) for k, v in timing.items() if k.endswith("_ms")},
         "work": {k: timing[k] for k in ("clique_entries", "wedges_light", "wedges_heavy",
                                          "wedges_dense", "dense_hubs", "heavy_items")},
