@@ -587,10 +587,9 @@ __global__ void k_hub_mark(HubArgs g) {
   for (int i = threadIdx.x; i < nl; i += blockDim.x) {
     const size_t v = (size_t)g.col2[a + i];
     if (SET) {
-      atomicOr(&g.mask[2 * v + (k >> 6)], bit);
+      atomicOr(&g.mask[kDenseWords * v + (k >> 6)], bit);
     } else {
-      g.mask[2 * v] = 0;
-      g.mask[2 * v + 1] = 0;
+      for (int w = 0; w < kDenseWords; w++) g.mask[kDenseWords * v + w] = 0;
     }
   }
 }
@@ -631,40 +630,56 @@ __global__ __launch_bounds__(256) void k_hub_short(HubArgs g) {
   __syncthreads();
   const int ylim = min(s_long, xs[0]);
   const ulonglong2 *M = reinterpret_cast<const ulonglong2 *>(g.mask);
+  constexpr int NH = kDenseWords / 2;  // 128-bit halves per vertex
   u64 acc = 0;
   for (int y = blockIdx.x * blockDim.x + threadIdx.x; y < ylim; y += gridDim.x * blockDim.x) {
     const int t = hubs_above(xs, g.nslab, y);
     if (t == 0) continue;
-    u64 P0[kShortBits], P1[kShortBits];
+    u64 P[kDenseWords][kShortBits];
 #pragma unroll
-    for (int j = 0; j < kShortBits; j++) P0[j] = P1[j] = 0;
+    for (int w = 0; w < kDenseWords; w++)
+#pragma unroll
+      for (int j = 0; j < kShortBits; j++) P[w][j] = 0;
     const int a = g.rp2[y], b = g.rp2[y + 1];
     int p = a;
-    for (; p + 4 <= b; p += 4) {
-      int v[4];
-      ulonglong2 mm[4];
+    for (; p + 2 <= b; p += 2) {
+      int v[2];
+      ulonglong2 mm[2][NH];
 #pragma unroll
-      for (int r = 0; r < 4; r++) v[r] = g.col2[p + r];
+      for (int r = 0; r < 2; r++) v[r] = g.col2[p + r];
 #pragma unroll
-      for (int r = 0; r < 4; r++) mm[r] = M[v[r]];
+      for (int r = 0; r < 2; r++)
 #pragma unroll
-      for (int r = 0; r < 4; r++) {
-        if (mm[r].x) plane_add(P0, mm[r].x);
-        if (mm[r].y) plane_add(P1, mm[r].y);
-      }
+        for (int h = 0; h < NH; h++) mm[r][h] = M[(size_t)v[r] * NH + h];
+#pragma unroll
+      for (int r = 0; r < 2; r++)
+#pragma unroll
+        for (int h = 0; h < NH; h++) {
+          if (mm[r][h].x) plane_add(P[2 * h], mm[r][h].x);
+          if (mm[r][h].y) plane_add(P[2 * h + 1], mm[r][h].y);
+        }
     }
     for (; p < b; p++) {
-      const ulonglong2 mm = M[g.col2[p]];
-      if (mm.x) plane_add(P0, mm.x);
-      if (mm.y) plane_add(P1, mm.y);
+      const int v = g.col2[p];
+#pragma unroll
+      for (int h = 0; h < NH; h++) {
+        const ulonglong2 mm = M[(size_t)v * NH + h];
+        if (mm.x) plane_add(P[2 * h], mm.x);
+        if (mm.y) plane_add(P[2 * h + 1], mm.y);
+      }
     }
     u64 any = 0;
 #pragma unroll
-    for (int j = 0; j < kShortBits; j++) any |= P0[j] | P1[j];
+    for (int w = 0; w < kDenseWords; w++)
+#pragma unroll
+      for (int j = 0; j < kShortBits; j++) any |= P[w][j];
     if (!any) continue;
-    const u64 V0 = t >= 64 ? ~0ull : ((1ull << t) - 1);
-    const u64 V1 = t >= 128 ? ~0ull : (t > 64 ? ((1ull << (t - 64)) - 1) : 0ull);
-    acc += planes_pairs(P0, V0) + planes_pairs(P1, V1);
+#pragma unroll
+    for (int w = 0; w < kDenseWords; w++) {
+      const int tw = t - 64 * w;
+      const u64 V = tw >= 64 ? ~0ull : (tw > 0 ? ((1ull << tw) - 1) : 0ull);
+      acc += planes_pairs(P[w], V);
+    }
   }
   const u128 s = block_sum_u128((u128)acc, red);
   if (threadIdx.x == 0 && s) atomic_add_u128(g.c4ni, s);
@@ -691,23 +706,21 @@ __global__ __launch_bounds__(256) void k_hub_long(HubArgs g) {
     uint32_t *mine = cnt[threadIdx.x / kWave];
     const int a = g.rp2[y], b = g.rp2[y + 1];
     for (int p = a + threadIdx.x; p < b; p += blockDim.x) {
-      const ulonglong2 mm = M[g.col2[p]];
-      u64 m0 = mm.x, m1 = mm.y;
-      while (m0) {
-        const int k = __builtin_ctzll(m0);
-        m0 &= m0 - 1;
-        if (k < t) atomicAdd(&mine[k], 1u);
-      }
-      while (m1) {
-        const int k = 64 + __builtin_ctzll(m1);
-        m1 &= m1 - 1;
-        if (k < t) atomicAdd(&mine[k], 1u);
+      const size_t v = (size_t)g.col2[p];
+#pragma unroll
+      for (int w = 0; w < kDenseWords; w++) {
+        u64 m = g.mask[kDenseWords * v + w];
+        while (m) {
+          const int k = 64 * w + __builtin_ctzll(m);
+          m &= m - 1;
+          if (k < t) atomicAdd(&mine[k], 1u);
+        }
       }
     }
     __syncthreads();
-    if (threadIdx.x < t) {
+    for (int k = threadIdx.x; k < t; k += blockDim.x) {
       u64 c = 0;
-      for (int w = 0; w < 256 / kWave; w++) c += cnt[w][threadIdx.x];
+      for (int w = 0; w < 256 / kWave; w++) c += cnt[w][k];
       acc += (u128)choose2(c);
     }
     __syncthreads();

@@ -134,7 +134,7 @@ struct Dyn {
   int4 *items;
   u64 *hkeys, *hkeys_alt;
   int64_t *pcount;
-  u64 *hubmask;     // dense hub slabs: 2 mask words per vertex (global mode)
+  u64 *hubmask;     // dense hub slabs: kDenseWords mask words per vertex (global mode)
   int32_t *hubs;    // dense hubs, slab by slab, ranks descending in a slab
   u64 *hubw;        // wedge counts of the candidate hubs
 };
@@ -157,7 +157,7 @@ void alloc_dyn(Arena &a, const Plan &P, const DynNeed &d, Dyn &y) {
   y.hkeys_alt = a.take<u64>(nh);
   y.pcount = a.take<int64_t>(nh);
   const bool dense = !P.per_edge && d.nheavy > 0;
-  y.hubmask = dense ? a.take<u64>(2 * (size_t)P.n) : nullptr;
+  y.hubmask = dense ? a.take<u64>(kDenseWords * (size_t)P.n) : nullptr;
   y.hubs = dense ? a.take<int32_t>(kDenseHubMax) : nullptr;
   y.hubw = dense ? a.take<u64>(kDenseHubMax) : nullptr;
   if (a.measuring()) {
@@ -452,7 +452,7 @@ int run(const gc_csr *G, gc_u128 out17[17], int64_t *per_edge_out, int64_t *loca
     if (ndense > 0) {
       GC_TRY_HIP(hipMemcpyAsync(dy.hubs, hubs.data(), sizeof(int32_t) * ndense,
                                 hipMemcpyHostToDevice, s));
-      GC_TRY(fill<u64>(dy.hubmask, 0ull, 2 * n, s));
+      GC_TRY(fill<u64>(dy.hubmask, 0ull, kDenseWords * n, s));
     }
   }
   GC_TRY(expand_heavy_items(pp, dn.nheavy, ndense, hsorted,

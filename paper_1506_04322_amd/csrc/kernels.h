@@ -190,10 +190,11 @@ struct C4Args {
 // kDenseSlab at a time: every vertex v gets a mask whose bit k says that v is
 // a lower neighbour of hub k, and one pass over all rows y sums, per hub, the
 // mask bits of y's neighbours, which is c(x_k, y).
-constexpr int kDenseSlab = 128;        // hubs per slab: two mask words per vertex
+constexpr int kDenseSlab = 256;        // hubs per slab
+constexpr int kDenseWords = kDenseSlab / 64;  // mask words per vertex
 constexpr int kDenseHubMax = 8192;     // candidates examined by the host
 constexpr int kDenseShortDeg = 1023;   // rows up to this degree: one thread, 10 bit planes
-constexpr double kDenseSlabPs = 1.6e9;      // measured cost of one slab pass (R-MAT s22)
+constexpr double kDenseSlabPs = 2.9e9;      // measured cost of one slab pass (R-MAT s22)
 constexpr double kSparseWedgePs = 4.9;      // measured cost of one heavy wedge by work items
 struct HubArgs {
   const int32_t *rp2, *col2, *lcnt;

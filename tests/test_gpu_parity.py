@@ -251,7 +251,7 @@ def test_dense_hub_slabs_rmat17():
     assert got2 == want
 
 
-kDenseSlab = 128
+kDenseSlab = 256
 
 
 # ------------------------------------------------------------ per-edge local vectors
