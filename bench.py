@@ -88,7 +88,7 @@ def measured_traffic(kernel: str, workload: str, field: str = "traffic_bytes_per
 
 def roofline_from_timing(t: dict, per_edge: bool = False):
     """The dominant kernel, the heavy 4-cycle items (one launch, alone in its
-    phase; k_c4_heavy_bal for global counts, k_c4_heavy with per-edge
+    phase; k_c4_heavy_bal, its per-edge instantiation with per-edge
     outputs): its algorithmic bytes (4 B per wedge it aggregates) over its
     device time from HIP events on the library's stream."""
     ms, nbytes = t["cyc_heavy_ms"], 4 * t["wedges_heavy"]
@@ -96,7 +96,7 @@ def roofline_from_timing(t: dict, per_edge: bool = False):
     return "cyc_heavy", {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                          "traffic": None,
-                         "kernel": "k_c4_heavy" if per_edge else "k_c4_heavy_bal",
+                         "kernel": "k_c4_heavy_bal<true>" if per_edge else "k_c4_heavy_bal",
                          "phase_ms": round(ms, 3),
                          "bytes_per_launch": nbytes,
                          "work_unit": "wedges of the heavy work items x 4 B"}
