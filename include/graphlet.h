@@ -212,6 +212,22 @@ typedef struct gc_batch {
 int graphlet_count_batched(const gc_batch *b, int64_t *out, void *stream, uint32_t flags);
 
 /*
+ * Per-vertex counts of every graph of a batch (the node-level view of the
+ * per-edge local counts of Section 4.2, for the graph-classification batches
+ * of Section 6): for each vertex v of each graph and each of the 17 classes,
+ * the number of induced k-subsets of v's graph that contain v and induce that
+ * class, the same quantity graphlet_count_vertex gives for one graph.
+ *   b     as for graphlet_count_batched (same checks, same GC_VALIDATE)
+ *   out   DEVICE uint64[node_off[G]][17], vertex-major: the row of vertex i of
+ *         graph g is node_off[g] + i, its 17 counts in the order above (every
+ *         count fits 64 bits for graphs of at most GC_BATCH_MAX_N vertices)
+ * Summed over the vertices of a graph, the counts of a size-k class are k
+ * times that graph's count.  Errors as for graphlet_count_batched; out is
+ * not written on error.  Stream-ordered; returns when out is complete.
+ */
+int graphlet_batch_vertex(const gc_batch *b, uint64_t *out, void *stream, uint32_t flags);
+
+/*
  * Graphlet frequency distributions of a batch (the normalised counts used to
  * compare and classify graphs, Section 6.1): for each graph and each size
  * k = 2, 3, 4, every count of size k divided by the sum of the counts of

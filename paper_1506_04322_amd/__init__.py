@@ -63,6 +63,7 @@ EXPORTS = [
     "graphlet_count_vertex",
     "graphlet_update_edge",
     "graphlet_count_batched",
+    "graphlet_batch_vertex",
     "graphlet_batch_gfd",
     "graphlet_batch_plan_create",
     "graphlet_batch_plan_run",
@@ -143,6 +144,8 @@ def load():
     lib.graphlet_batch_gfd.restype = ctypes.c_int
     lib.graphlet_count_batched.argtypes = [ctypes.POINTER(_Batch), P, P, ctypes.c_uint32]
     lib.graphlet_count_batched.restype = ctypes.c_int
+    lib.graphlet_batch_vertex.argtypes = [ctypes.POINTER(_Batch), P, P, ctypes.c_uint32]
+    lib.graphlet_batch_vertex.restype = ctypes.c_int
     lib.graphlet_batch_plan_create.argtypes = [ctypes.POINTER(_Batch), P, ctypes.c_int, P,
                                                ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p)]
     lib.graphlet_batch_plan_create.restype = ctypes.c_int
@@ -365,6 +368,32 @@ def graphlet_count_batched(node_off, row_ptr, col, out=None, stream=None, valida
     if rc != 0:
         raise GraphletError(rc, graphlet_last_error())
     return out[:G]
+
+
+def graphlet_batch_vertex(node_off, row_ptr, col, out=None, stream=None, validate=False):
+    """[node_off[G], 17] uint64 device tensor: for every vertex of every graph
+    of a batch, the number of k-subsets of its graph containing it by induced
+    class (order of NAMES); row node_off[g] + i is vertex i of graph g."""
+    import torch
+
+    lib = load()
+    _check_dev(node_off, torch.int64, "node_off")
+    _check_dev(row_ptr, torch.int32, "row_ptr")
+    _check_dev(col, torch.int32, "col")
+    G = node_off.numel() - 1
+    nv = int(node_off[-1].item()) if G > 0 else 0
+    if out is None:
+        out = torch.empty((max(nv, 1), 17), dtype=torch.uint64, device=node_off.device)
+    else:
+        _check_dev(out, torch.uint64, "out")
+        if out.numel() < 17 * nv:
+            raise ValueError("out too small")
+    b = _Batch(G, node_off.data_ptr(), row_ptr.data_ptr(), col.data_ptr() if col.numel() else 0)
+    rc = lib.graphlet_batch_vertex(ctypes.byref(b), out.data_ptr(), _stream_ptr(stream),
+                                   GC_VALIDATE if validate else 0)
+    if rc != 0:
+        raise GraphletError(rc, graphlet_last_error())
+    return out.view(-1)[:17 * nv].view(nv, 17)
 
 
 def graphlet_batch_gfd(counts, connected_only: bool = False, stream=None):

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgraphlet.so")
 SOURCES = ["graphlet.hip", "prepass.hip", "cliques.hip", "cycles.hip", "step3.hip",
-           "primitives.hip", "batched.hip", "update.hip", "vertex.hip", "server.cpp"]
+           "primitives.hip", "batched.hip", "update.hip", "vertex.hip",
+           "batched_vertex.hip", "server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

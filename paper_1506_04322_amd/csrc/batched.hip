@@ -528,6 +528,11 @@ int time_plan(gc_batch_plan *p, hipStream_t s, double *ms) {
   return rc;
 }
 
+}  // namespace
+
+// Validates a batch (GC_VALIDATE: the full CSR contract of every graph) and
+// returns, per graph, its vertex count and its adjacency-list length.  Shared
+// with the batched per-vertex entry point.
 int check_batch(const gc_batch *b, int64_t *out, hipStream_t s, uint32_t flags,
                 std::vector<int64_t> *sizes) {
   if (!b || b->graphs < 0 || b->graphs > (1ll << 30) ||
@@ -569,6 +574,8 @@ int check_batch(const gc_batch *b, int64_t *out, hipStream_t s, uint32_t flags,
   }
   return GC_OK;
 }
+
+namespace {
 
 void destroy_plan(gc_batch_plan *p) {
   if (!p) return;

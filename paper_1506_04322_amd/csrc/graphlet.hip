@@ -856,6 +856,6 @@ int graphlet_last_timing(gc_timing *out) {
   return GC_OK;
 }
 
-const char *graphlet_version(void) { return "graphlet-mi355x 0.4"; }
+const char *graphlet_version(void) { return "graphlet-mi355x 0.5"; }
 
 }  // extern "C"

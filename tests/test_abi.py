@@ -47,6 +47,7 @@ def test_null_arguments_are_rejected_without_touching_a_device():
     bad = gl._Csr(5, 3, 0, 0)  # odd nnz
     assert lib.graphlet_count(ctypes.byref(bad), (gl._U128 * 17)(), None, None, 0, None, 0) == -1
     assert lib.graphlet_count_batched(None, None, None, 0) == -1
+    assert lib.graphlet_batch_vertex(None, None, None, 0) == -1
     assert lib.graphlet_count_vertex(None, (gl._U128 * 17)(), None, None, 0, None, 0) == -1
     assert "null" in gl.graphlet_last_error()
 

@@ -650,6 +650,108 @@ def test_batch_gfd_exact():
             np.testing.assert_array_equal(c[:, 6:17].sum(1), n * (n - 1) * (n - 2) * (n - 3) // 24)
 
 
+# ------------------------------------------------------------ batched per-vertex counts
+
+
+def batch_vertex_gpu(b, validate=True):
+    out = gl.graphlet_batch_vertex(dev(b.node_off), dev(b.row_ptr), dev(b.col),
+                                   validate=validate)
+    return out.cpu().numpy()
+
+
+def check_batch_vertex_sums(b, counts, V):
+    # per graph: summed over its vertices, a size-k class is seen k times;
+    # each vertex's row is a census of the subsets containing it
+    for i in range(b.graphs):
+        a, e = int(b.node_off[i]), int(b.node_off[i + 1])
+        n = e - a
+        Vi = V[a:e].astype(np.int64)
+        np.testing.assert_array_equal(Vi.sum(0), np.array(oracle.CLASS_K) * counts[i])
+        if n:
+            np.testing.assert_array_equal(Vi[:, 0], np.diff(b.row_ptr[a:e + 1]))
+            assert (Vi[:, :2].sum(1) == n - 1).all()
+            assert (Vi[:, 2:6].sum(1) == comb(n - 1, 2)).all()
+            assert (Vi[:, 6:].sum(1) == comb(n - 1, 3)).all()
+
+
+def test_batch_vertex_mixed_sizes_vs_oracle():
+    rng = np.random.default_rng(91)
+    graphs = []
+    for n in [0, 1, 2, 3, 4, 5, 9, 17, 33, 60, 64, 65, 128, 129, 256, 257, 512, 513, 1024]:
+        graphs.append(rand_graph(rng, n, float(rng.uniform(0.02, 0.35))))
+    graphs.append(graphgen.from_edges(50, [(a, b) for a in range(50) for b in range(a + 1, 50)]))
+    graphs.append(graphgen.from_edges(300, [(0, i) for i in range(1, 300)]))
+    graphs.append(graphgen.rgg_torus(400, 8.0, 9))
+    b = make_batch(graphs)
+    V = batch_vertex_gpu(b)
+    assert V.shape == (int(b.node_off[-1]), 17)
+    counts = batched_gpu(b)
+    check_batch_vertex_sums(b, counts, V)
+    for i, g in enumerate(graphs):
+        Vi = V[b.node_off[i]:b.node_off[i + 1]]
+        if g.n <= 60:
+            np.testing.assert_array_equal(Vi, oracle.vertex_bruteforce(g).astype(np.uint64))
+        else:
+            vs = _sampled_vertices(g, 12, 100 + i)
+            np.testing.assert_array_equal(Vi[vs], oracle.vertex_by_deletion(g, vs))
+
+
+def test_batch_vertex_config4_sample():
+    b = C.batch8192()
+    V = batch_vertex_gpu(b, validate=False)
+    counts = batched_gpu(b)
+    check_batch_vertex_sums(b, counts, V)
+    rng = np.random.default_rng(41)
+    for i in rng.choice(b.graphs, 24, replace=False):
+        g = b.graph(int(i))
+        Vi = V[b.node_off[i]:b.node_off[i + 1]]
+        vs = _sampled_vertices(g, 6, int(i))
+        np.testing.assert_array_equal(Vi[vs], oracle.vertex_by_deletion(g, vs))
+
+
+def test_batch_vertex_equals_single_graph_path():
+    b = C.batch8192(48)
+    V = batch_vertex_gpu(b)
+    for i in range(b.graphs):
+        _, Vg = gpu_vertex(b.graph(i), validate=False)
+        np.testing.assert_array_equal(V[b.node_off[i]:b.node_off[i + 1]], Vg)
+
+
+def test_batch_vertex_degenerate_batches():
+    import torch
+
+    # no graphs: nothing to do
+    empty = make_batch([])
+    assert batch_vertex_gpu(empty).shape == (0, 17)
+    # only vertex-free graphs: nothing written
+    b = make_batch([graphgen.from_edges(0, []), graphgen.from_edges(0, [])])
+    assert batch_vertex_gpu(b).shape == (0, 17)
+    # edgeless graphs: every vertex sits in the fully disconnected classes only
+    b = make_batch([graphgen.from_edges(7, []), graphgen.from_edges(0, []),
+                    graphgen.from_edges(2, [(0, 1)])])
+    V = batch_vertex_gpu(b)
+    want = np.zeros((9, 17), np.uint64)
+    want[:7, 1], want[:7, 5], want[:7, 16] = 6, 15, 20
+    want[7:, 0] = 1
+    np.testing.assert_array_equal(V, want)
+    # a caller's buffer that is too small is refused before the call
+    with pytest.raises(ValueError):
+        gl.graphlet_batch_vertex(dev(b.node_off), dev(b.row_ptr), dev(b.col),
+                                 out=torch.empty((2, 17), dtype=torch.uint64, device="cuda:0"))
+
+
+def test_batch_vertex_rejects_invalid_batches():
+    g = graphgen.from_edges(1100, [(0, 1)])
+    with pytest.raises(gl.GraphletError) as e:
+        batch_vertex_gpu(make_batch([g]))
+    assert e.value.code == -5
+    # an asymmetric list (0 -> 1 without 1 -> 0, padded to an even length)
+    bad = graphgen.Batch(np.array([0, 3], np.int64), np.zeros(1, np.int64),
+                         np.array([0, 2, 2, 2], np.int32), np.array([1, 2], np.int32))
+    with pytest.raises(gl.GraphletError):
+        batch_vertex_gpu(bad, validate=True)
+
+
 # ------------------------------------------------------------ batched plans
 
 CLASS_SETS = [[16], [4, 16], [1, 4, 16], [4, 10, 16], [2, 6, 10, 16], [1, 2, 4, 6, 8, 10, 12, 16]]
