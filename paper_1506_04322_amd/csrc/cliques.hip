@@ -71,30 +71,63 @@ __device__ __forceinline__ int hfind(const int32_t *H, const int32_t *U, uint32_
 // starts at P[o] and reads list position V[o]) are taken in slabs of
 // kWave * RUN per wave: in step r, lane L takes candidate s0 + r * kWave + L,
 // so the lanes of each load and of each per-entry atomic touch consecutive
-// entries.  Each lane finds its row by binary search between the rows of
-// the slab's first and last candidates.  pos[r] = -1 past the end.
+// entries.  The rows of the slab's first and last candidates are found by
+// galloping forward from a cursor (a wave's slabs advance through the rows),
+// each lane finds the row of its first candidate by binary search between
+// them, then follows its later candidates forward (rows are long on
+// average: most steps stay in the row).  pos[r] = -1 past the end.
+
+// Largest o in [from, n) with P[o] <= x, given P[from] <= x (P increasing).
+__device__ __forceinline__ int gallop_row(const int32_t *P, int n, int from, int x) {
+  int lo = from, hi = from + 1, step = 1;
+  while (hi < n && P[hi] <= x) {
+    lo = hi;
+    step <<= 1;
+    hi = lo + step;
+  }
+  hi = min(hi, n);  // P[lo] <= x, and hi == n or P[hi] > x
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (P[mid] <= x) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
 template <int RUN>
 __device__ __forceinline__ void slab_positions(const int32_t *P, const int32_t *V,
                                                const int32_t *rid, int nr, int total, int s0,
-                                               int (&pos)[RUN], int (&row)[RUN]) {
+                                               int &cursor, int (&pos)[RUN], int (&row)[RUN]) {
   const int lane = lane_id();
-  const int ia = upper_index_dev<int32_t>(P, nr, s0);
-  const int ib = upper_index_dev<int32_t>(P, nr, min(s0 + kWave * RUN, total) - 1) + 1;
+  const int ia = gallop_row(P, nr, cursor, s0);
+  const int ib = gallop_row(P, nr, ia, min(s0 + kWave * RUN, total) - 1) + 1;
+  cursor = ia;
+  int lo = ia;  // P[lo] <= t < P[lo + 1] for the lane's current candidate t
+  if (s0 + lane < total) {
+    int hi = ib;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (P[mid] <= s0 + lane) lo = mid;
+      else hi = mid;
+    }
+  }
 #pragma unroll
   for (int r = 0; r < RUN; r++) {
     const int t = s0 + r * kWave + lane;
     pos[r] = -1;
     if (t < total) {
-      int lo = ia, hi = ib;  // P[ia] <= t < P[ib]
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (P[mid] <= t) lo = mid;
-        else hi = mid;
-      }
+      while (lo + 1 < ib && P[lo + 1] <= t) lo++;
       pos[r] = V[lo] + (t - P[lo]);
       row[r] = rid[lo];
     }
   }
+}
+
+// Bit filter of the hashed set: one bit per 2^FLOG slot of the same
+// multiplicative hash; a candidate whose bit is clear is not in the set.
+template <int FLOG>
+__device__ __forceinline__ uint32_t fslot(int32_t x) {
+  return ((uint32_t)x * 2654435761u) >> (32 - FLOG);
 }
 
 // Row i of the triangular layout holds words [i >> 6, W) of the upper half.
@@ -105,13 +138,20 @@ __device__ __forceinline__ int tri_off(int i, int W) {
 
 // ------------------------------------------------------------ global mode
 
+// The three smaller shapes fit 8 waves per SIMD by LDS; their registers are
+// held to 64 per lane so that they do (the issue of VALU work bounds them).
 template <int BLOCK, int KCAP, int HS>
-__global__ __launch_bounds__(BLOCK) void k_tk_up(TkArgs g) {
+__global__ __launch_bounds__(BLOCK)
+__attribute__((amdgpu_waves_per_eu(BLOCK <= 512 ? 8 : 1))) void k_tk_up(TkArgs g) {
   constexpr int WC = (KCAP + 63) / 64;
   constexpr int RWORDS = 32 * WC * (WC + 1);  // tri_off(64 WC, WC)
   constexpr int RUN = 8;                       // consecutive entries per thread
+  // filter of U(u): 8 bits per hash slot (4 for the two largest tables),
+  // so at most 1 in 32 candidates outside U(u) reaches the hash table
+  constexpr int FLOG = (31 - __builtin_clz(HS)) + (HS <= 1024 ? 3 : 2);
+  constexpr int FW = (1 << FLOG) / 32;
   __shared__ int32_t U[KCAP], V[KCAP], P[KCAP + 1], rid[KCAP], H[HS], sums[BLOCK];
-  __shared__ uint32_t colcnt[KCAP];
+  __shared__ uint32_t colcnt[KCAP], F[FW];
   __shared__ u64 R[RWORDS];
   __shared__ u64 red[32];
   __shared__ int next, nrows;
@@ -132,6 +172,7 @@ __global__ __launch_bounds__(BLOCK) void k_tk_up(TkArgs g) {
       colcnt[i] = 0;
     }
     for (int h = tid; h < hs; h += BLOCK) H[h] = 0;
+    for (int w = tid; w < FW; w += BLOCK) F[w] = 0;
     for (int w = tid; w < rwords; w += BLOCK) R[w] = 0;
     if (tid == 0) {
       next = 0;
@@ -147,6 +188,8 @@ __global__ __launch_bounds__(BLOCK) void k_tk_up(TkArgs g) {
         len = g.ucnt[v];
         uint32_t h = hslot(v, hbits);
         while (atomicCAS(&H[h], 0, i + 1) != 0) h = (h + 1) & mask;
+        const uint32_t f = fslot<FLOG>(v);
+        atomicOr(&F[f >> 5], 1u << (f & 31));
       }
       const bool keep = len > 0;
       const u64 m = __ballot(keep);
@@ -167,14 +210,17 @@ __global__ __launch_bounds__(BLOCK) void k_tk_up(TkArgs g) {
     // Build: every entry x of U(U_i) that lies in U(u) is a triangle.  Each
     // thread takes RUN consecutive entries: positions first, then all loads,
     // then the LDS work, so RUN reads are in flight per thread.
+    int cursor = 0;  // row at or before the wave's next slab
     for (int s0 = (tid / kWave) * kWave * RUN; s0 < total; s0 += BLOCK * RUN) {
       int pos[RUN], row[RUN], xv[RUN];
-      slab_positions<RUN>(P, V, rid, nr, total, s0, pos, row);
+      slab_positions<RUN>(P, V, rid, nr, total, s0, cursor, pos, row);
 #pragma unroll
       for (int r = 0; r < RUN; r++) xv[r] = pos[r] >= 0 ? g.col2[pos[r]] : -1;
 #pragma unroll
       for (int r = 0; r < RUN; r++) {
         if (pos[r] < 0) continue;
+        const uint32_t f = fslot<FLOG>(xv[r]);
+        if (!((F[f >> 5] >> (f & 31)) & 1u)) continue;
         const int j = hfind(H, U, mask, hbits, xv[r]);
         if (j >= 0) {
           const int ir = row[r];
@@ -291,9 +337,10 @@ __global__ __launch_bounds__(BLOCK) void k_tk_pe(TkArgs g) {
     block_scan_excl<BLOCK>(P, nr, sums);
     const int total = P[nr];
     for (int pass = 0; pass < 2; pass++) {
+      int cursor = 0;  // row at or before the wave's next slab
       for (int s0 = (tid / kWave) * kWave * RUN; s0 < total; s0 += BLOCK * RUN) {
         int pos[RUN], row[RUN], xv[RUN];
-        slab_positions<RUN>(P, V, rid, nr, total, s0, pos, row);
+        slab_positions<RUN>(P, V, rid, nr, total, s0, cursor, pos, row);
 #pragma unroll
         for (int r = 0; r < RUN; r++) xv[r] = pos[r] >= 0 ? g.col2[pos[r]] : -1;
 #pragma unroll
