@@ -111,14 +111,25 @@ __device__ __forceinline__ void slab_positions(const int32_t *P, const int32_t *
       else hi = mid;
     }
   }
+  // the current row's start, end, list position and id, reloaded only when a
+  // candidate crosses into a later row
+  int p_lo = P[lo], p_next = lo + 1 < ib ? P[lo + 1] : total, v_lo = V[lo], r_lo = rid[lo];
 #pragma unroll
   for (int r = 0; r < RUN; r++) {
     const int t = s0 + r * kWave + lane;
     pos[r] = -1;
     if (t < total) {
-      while (lo + 1 < ib && P[lo + 1] <= t) lo++;
-      pos[r] = V[lo] + (t - P[lo]);
-      row[r] = rid[lo];
+      if (t >= p_next) {
+        do {
+          lo++;
+        } while (lo + 1 < ib && P[lo + 1] <= t);
+        p_lo = P[lo];
+        p_next = lo + 1 < ib ? P[lo + 1] : total;
+        v_lo = V[lo];
+        r_lo = rid[lo];
+      }
+      pos[r] = v_lo + (t - p_lo);
+      row[r] = r_lo;
     }
   }
 }
@@ -281,8 +292,10 @@ template <int BLOCK, int KCAP, int HS, bool GR>
 __global__ __launch_bounds__(BLOCK) void k_tk_pe(TkArgs g) {
   constexpr int WC = (KCAP + 63) / 64;
   constexpr int RUN = 8;
+  constexpr int FLOG = (31 - __builtin_clz(HS)) + (HS <= 1024 ? 3 : 2);  // as in k_tk_up
+  constexpr int FW = (1 << FLOG) / 32;
   __shared__ int32_t U[KCAP], V[KCAP], P[KCAP + 1], rid[KCAP], H[HS], sums[BLOCK];
-  __shared__ uint32_t Tu[KCAP], A1[KCAP];
+  __shared__ uint32_t Tu[KCAP], A1[KCAP], F[FW];
   __shared__ u64 A2[KCAP];
   __shared__ u64 Rl[GR ? 1 : KCAP * WC];
   __shared__ int nrows;
@@ -308,6 +321,7 @@ __global__ __launch_bounds__(BLOCK) void k_tk_pe(TkArgs g) {
       A2[i] = 0;
     }
     for (int h = tid; h < hs; h += BLOCK) H[h] = 0;
+    for (int w = tid; w < FW; w += BLOCK) F[w] = 0;
     for (int w = tid; w < k * W; w += BLOCK) R[w] = 0;
     if (tid == 0) nrows = 0;
     __syncthreads();
@@ -319,6 +333,8 @@ __global__ __launch_bounds__(BLOCK) void k_tk_pe(TkArgs g) {
         len = g.ucnt[v];
         uint32_t h = hslot(v, hbits);
         while (atomicCAS(&H[h], 0, i + 1) != 0) h = (h + 1) & mask;
+        const uint32_t f = fslot<FLOG>(v);
+        atomicOr(&F[f >> 5], 1u << (f & 31));
       }
       const bool keep = len > 0;
       const u64 m = __ballot(keep);
@@ -346,6 +362,8 @@ __global__ __launch_bounds__(BLOCK) void k_tk_pe(TkArgs g) {
 #pragma unroll
         for (int r = 0; r < RUN; r++) {
           if (pos[r] < 0) continue;
+          const uint32_t f = fslot<FLOG>(xv[r]);
+          if (!((F[f >> 5] >> (f & 31)) & 1u)) continue;
           const int j = hfind(H, U, mask, hbits, xv[r]);
           if (j < 0) continue;
           const int ir = row[r];  // j > ir: U(U_i) lies above U_i
