@@ -34,6 +34,7 @@
 // so its row reads are broadcasts.  Graphs have at most GC_BATCH_MAX_N
 // vertices, so every count and LDS sum fits its type.
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -269,6 +270,30 @@ BvKernel bv_kernel(int cls) {
   }
 }
 
+// Streams on which the size classes run side by side (default priority,
+// created once per device and kept for the process), and the lock that
+// makes one call's fork and join a unit.
+constexpr int kBvMaxDevices = 64;
+std::mutex g_bv_mu;
+hipStream_t g_bv_streams[kBvMaxDevices][kBvClasses];
+bool g_bv_ready[kBvMaxDevices];
+
+hipError_t class_streams(int dev, hipStream_t **out) {
+  if (dev < 0 || dev >= kBvMaxDevices) return hipErrorInvalidDevice;
+  if (!g_bv_ready[dev]) {
+    for (int c = 0; c < kBvClasses; c++) {
+      const hipError_t e = hipStreamCreateWithFlags(&g_bv_streams[dev][c], hipStreamNonBlocking);
+      if (e != hipSuccess) {
+        for (int k = 0; k < c; k++) (void)hipStreamDestroy(g_bv_streams[dev][k]);
+        return e;
+      }
+    }
+    g_bv_ready[dev] = true;
+  }
+  *out = g_bv_streams[dev];
+  return hipSuccess;
+}
+
 // Estimated work of one graph: the all-pairs pass, the triangle visits and
 // the per-edge row intersections.
 double bv_cost(int64_t n, int64_t nnz) {
@@ -321,9 +346,20 @@ extern "C" int graphlet_batch_vertex(const gc_batch *b, uint64_t *out, void *str
                                   hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemsetAsync(dnext, 0, sizeof(int32_t) * gc::kBvClasses, s);
     int dev = 0, cus = 256;
-    if (e == hipSuccess && hipGetDevice(&dev) == hipSuccess)
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess)
       (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    for (int c = 0; c < gc::kBvClasses && e == hipSuccess; c++) {
+    // the classes run on streams of their own, after the uploads on s, and s
+    // waits for all of them (largest class first, so its tail overlaps the rest)
+    std::lock_guard<std::mutex> lk(gc::g_bv_mu);
+    hipStream_t *cs = nullptr;
+    if (e == hipSuccess) e = gc::class_streams(dev, &cs);
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> done;
+    std::vector<int> launched;
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(fork, s);
+    for (int c = gc::kBvClasses - 1; c >= 0 && e == hipSuccess; c--) {
       const int count = (int)bins[c].size();
       if (count == 0) continue;
       const int W = gc::kBvWords[c];
@@ -341,13 +377,29 @@ extern "C" int graphlet_batch_vertex(const gc_batch *b, uint64_t *out, void *str
                                                          lds);
       if (e != hipSuccess) break;
       const int grid = std::max(1, std::min(count, cus * std::max(per_cu, 1)));
-      k<<<grid, gc::kBvBlock, lds, s>>>(b->node_off, b->row_ptr, b->col, dlist + first[c], count,
-                                        dnext + c, reinterpret_cast<gc::u64 *>(out));
+      hipEvent_t ev = nullptr;
+      e = hipStreamWaitEvent(cs[c], fork, 0);
+      if (e != hipSuccess) break;
+      k<<<grid, gc::kBvBlock, lds, cs[c]>>>(b->node_off, b->row_ptr, b->col, dlist + first[c],
+                                            count, dnext + c, reinterpret_cast<gc::u64 *>(out));
       e = hipGetLastError();
+      if (e == hipSuccess) launched.push_back(c);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+      if (e == hipSuccess) {
+        done.push_back(ev);
+        e = hipEventRecord(ev, cs[c]);
+      }
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, ev, 0);
     }
+    // on an error part way, the classes already launched finish before the
+    // order and counters are freed
+    if (e != hipSuccess)
+      for (int c : launched) (void)hipStreamSynchronize(cs[c]);
     (void)hipFreeAsync(dlist, s);
     const hipError_t f = hipStreamSynchronize(s);
     if (e == hipSuccess) e = f;
+    for (hipEvent_t ev : done) (void)hipEventDestroy(ev);
+    if (fork) (void)hipEventDestroy(fork);
     if (e != hipSuccess) {
       gc::set_error("batched vertex counts: %s", hipGetErrorString(e));
       return GC_EHIP;
