@@ -223,8 +223,9 @@ int graphlet_count_batched(const gc_batch *b, int64_t *out, void *stream, uint32
  *         count fits 64 bits for graphs of at most GC_BATCH_MAX_N vertices)
  * Summed over the vertices of a graph, the counts of a size-k class are k
  * times that graph's count.  Errors as for graphlet_count_batched; out is
- * not written on error.  Stream-ordered; returns when out is complete.  The
- * size classes run on streams of the library's own (created on first use,
+ * not written when the checks fail (a HIP error part way may leave some
+ * rows written).  Stream-ordered; returns when out is complete.  The size
+ * classes run on streams of the library's own (created on first use,
  * one set per device, kept until the process ends), joined to `stream`;
  * calls from several host threads run one after another.
  */
