@@ -740,6 +740,40 @@ def test_batch_vertex_degenerate_batches():
                                  out=torch.empty((2, 17), dtype=torch.uint64, device="cuda:0"))
 
 
+def test_batch_vertex_concurrent_callers():
+    # two host threads, each on a stream of its own, share the library's
+    # class streams: every call must still equal the single-threaded result
+    import threading
+
+    import torch
+
+    b1, b2 = C.batch8192(96), make_batch([rand_graph(np.random.default_rng(s), n, 0.2)
+                                          for s, n in enumerate([30, 70, 150, 300, 600, 900])])
+    want = [batch_vertex_gpu(b1), batch_vertex_gpu(b2)]
+    dev_b = [tuple(dev(x) for x in (b.node_off, b.row_ptr, b.col)) for b in (b1, b2)]
+    got, errs = [[], []], []
+
+    def worker(k):
+        try:
+            st = torch.cuda.Stream()
+            for _ in range(4):
+                out = gl.graphlet_batch_vertex(*dev_b[k], stream=st)
+                got[k].append(out.cpu().numpy())
+        except Exception as e:  # reported below, on the main thread
+            errs.append(e)
+
+    ts = [threading.Thread(target=worker, args=(k,)) for k in (0, 1)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert not errs, errs
+    for k in (0, 1):
+        assert len(got[k]) == 4
+        for g in got[k]:
+            np.testing.assert_array_equal(g, want[k])
+
+
 def test_batch_vertex_rejects_invalid_batches():
     g = graphgen.from_edges(1100, [(0, 1)])
     with pytest.raises(gl.GraphletError) as e:
