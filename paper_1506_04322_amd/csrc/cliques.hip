@@ -156,7 +156,10 @@ __global__ __launch_bounds__(BLOCK)
 __attribute__((amdgpu_waves_per_eu(BLOCK <= 512 ? 8 : 1))) void k_tk_up(TkArgs g) {
   constexpr int WC = (KCAP + 63) / 64;
   constexpr int RWORDS = 32 * WC * (WC + 1);  // tri_off(64 WC, WC)
-  constexpr int RUN = 8;                       // consecutive entries per thread
+  // candidates per lane per slab, all loaded before any is probed; the
+  // 1024-thread shape is held to 4 waves per SIMD by LDS, not registers, so
+  // it keeps twice as many loads in flight
+  constexpr int RUN = BLOCK == 1024 ? 16 : 8;
   // filter of U(u): 8 bits per hash slot (4 for the two largest tables),
   // so at most 1 in 32 candidates outside U(u) reaches the hash table
   constexpr int FLOG = (31 - __builtin_clz(HS)) + (HS <= 1024 ? 3 : 2);
