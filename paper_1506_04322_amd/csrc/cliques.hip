@@ -291,7 +291,9 @@ __attribute__((amdgpu_waves_per_eu(BLOCK <= 512 ? 8 : 1))) void k_tk_up(TkArgs g
 //     is seen from two local edges at U_i) to edges (u, U_i) and (u, U_j);
 //   |Tri(u,U_i)| + |Tri(u,U_j)| - 2 goes to D of the edge, and
 //   |Tri(u,U_j)| + |Tri(U_i,U_j)| - 2 to D of (u, U_i) (and symmetrically).
-template <int BLOCK, int KCAP, int HS, bool GR>
+// Vertices of the list with k <= KMIN (or k > KCAP) are left to another
+// launch over the same list.
+template <int BLOCK, int KCAP, int HS, bool GR, int KMIN = 0>
 __global__ __launch_bounds__(BLOCK) void k_tk_pe(TkArgs g) {
   constexpr int WC = (KCAP + 63) / 64;
   constexpr int RUN = 8;
@@ -311,6 +313,7 @@ __global__ __launch_bounds__(BLOCK) void k_tk_pe(TkArgs g) {
   for (int it = blockIdx.x; it < g.nlist; it += gridDim.x) {
     const int u = g.list[it];
     const int k = g.ucnt[u];
+    if (k <= KMIN || k > KCAP) continue;  // the same on every thread
     const int base = g.ustart[u];
     const int W = (k + 63) >> 6;
     int hs = 64;
@@ -525,6 +528,10 @@ __global__ __launch_bounds__(BLOCK) void k_tk_global(TkArgs g) {
 
 }  // namespace
 
+// Largest k of the per-edge 1024-thread class whose symmetric rows stay in LDS.
+constexpr int kTkPeLds = 896;
+static_assert(kTkLim2 < kTkPeLds && kTkPeLds < kTkLim3, "splits the 1024-thread class");
+
 int launch_cliques(TkArgs g, int bin, bool per_edge, hipStream_t s) {
   if (g.nlist <= 0) return GC_OK;
   auto grid = [&](int cap) { return (unsigned)std::min(g.nlist, cap); };
@@ -541,8 +548,13 @@ int launch_cliques(TkArgs g, int bin, bool per_edge, hipStream_t s) {
       case 0: k_tk_pe<64, kTkLim0, 256, false><<<grid(65536), 64, 0, s>>>(g); break;
       case 1: k_tk_pe<256, kTkLim1, 1024, false><<<grid(16384), 256, 0, s>>>(g); break;
       case 2: k_tk_pe<512, kTkLim2, 2048, false><<<grid(8192), 512, 0, s>>>(g); break;
-      // rows of 1088 vertices (148 KB) do not fit beside the lists: global slot
-      case 3: k_tk_pe<1024, kTkLim3, 4096, true><<<grid(kTkGlobalSlots), 1024, 0, s>>>(g); break;
+      // symmetric rows of up to 896 vertices (98 KB) fit beside the lists;
+      // those of up to 1088 (148 KB) take a global slot
+      case 3:
+        k_tk_pe<1024, kTkPeLds, 4096, false><<<grid(4096), 1024, 0, s>>>(g);
+        GC_TRY_HIP(hipGetLastError());
+        k_tk_pe<1024, kTkLim3, 4096, true, kTkPeLds><<<grid(kTkGlobalSlots), 1024, 0, s>>>(g);
+        break;
       default: k_tk_global<256, true><<<grid(kTkGlobalSlots), 256, 0, s>>>(g); break;
     }
   }
