@@ -14,9 +14,13 @@
 //
 // Global mode keeps only the upper half of the local adjacency (bit j > i in
 // row i), packed triangularly; a column counter per local vertex gives the
-// lower half's contribution to |Tri|.  U(u) is indexed by an LDS hash.
-// Per-edge mode keeps symmetric rows, so that every local edge can read its
-// common-neighbour count (4-cliques through that edge).
+// lower half's contribution to |Tri|.  U(u) is indexed by an LDS hash, with
+// a bit filter in front of it: most candidates are not in U(u), and one LDS
+// read turns them away (the kernels are bound by instruction issue, not by
+// the gathers).  Per-edge mode keeps symmetric rows, so that every local
+// edge can read its common-neighbour count (4-cliques through that edge);
+// rows of up to 896 local vertices stay in LDS, larger ones (up to 1088)
+// use a per-workgroup slot in global memory.
 #include <algorithm>
 
 #include "kernels.h"
