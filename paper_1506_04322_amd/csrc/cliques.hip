@@ -305,7 +305,7 @@ __global__ __launch_bounds__(BLOCK) void k_tk_pe(TkArgs g) {
   constexpr int FW = (1 << FLOG) / 32;
   __shared__ int32_t U[KCAP], V[KCAP], P[KCAP + 1], rid[KCAP], H[HS], sums[BLOCK];
   __shared__ uint32_t Tu[KCAP], A1[KCAP], F[FW];
-  __shared__ u64 A2[KCAP];
+  __shared__ u64 A2[KCAP], B2[KCAP];  // B2: degree sums for edges (u, U_i)
   __shared__ u64 Rl[GR ? 1 : KCAP * WC];
   __shared__ int nrows;
   const int tid = threadIdx.x;
@@ -329,6 +329,7 @@ __global__ __launch_bounds__(BLOCK) void k_tk_pe(TkArgs g) {
       Tu[i] = g.T[base + i];
       A1[i] = 0;
       A2[i] = 0;
+      B2[i] = 0;
     }
     for (int h = tid; h < hs; h += BLOCK) H[h] = 0;
     for (int w = tid; w < FW; w += BLOCK) F[w] = 0;
@@ -397,8 +398,8 @@ __global__ __launch_bounds__(BLOCK) void k_tk_pe(TkArgs g) {
           atomicAdd(&A2[j], (u64)Tu[ir] + tij - 2);
           if (g.Bw) {  // local vectors: degrees of the third vertex of the triangle
             atomicAdd(&g.Bw[p], (u64)g.deg2[u]);
-            atomicAdd(&g.Bw[base + ir], (u64)g.deg2[U[j]]);
-            atomicAdd(&g.Bw[base + j], (u64)g.deg2[U[ir]]);
+            atomicAdd(&B2[ir], (u64)g.deg2[U[j]]);
+            atomicAdd(&B2[j], (u64)g.deg2[U[ir]]);
           }
         }
       }
@@ -407,6 +408,7 @@ __global__ __launch_bounds__(BLOCK) void k_tk_pe(TkArgs g) {
     for (int i = tid; i < k; i += BLOCK) {
       if (A1[i]) atomicAdd(&g.K4w[base + i], (u64)(A1[i] / 2));
       if (A2[i]) atomicAdd(&g.Dw[base + i], A2[i]);
+      if (B2[i]) atomicAdd(&g.Bw[base + i], B2[i]);  // zero unless g.Bw
     }
     __syncthreads();
   }
