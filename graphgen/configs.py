@@ -69,3 +69,17 @@ def serve_graph(kind: str, n: int, m: int, seed: int):
     if kind == "er":
         return er_gnm(n, m, seed)
     return chung_lu(n, SERVE["beta"], 1.0, int(m * 1.1), seed)
+
+
+# The serving benchmark replays a trace of SERVE_REQUESTS requests over a
+# pool of the graphs of its first SERVE_POOL requests.
+SERVE_REQUESTS = 1000
+SERVE_POOL = 96
+
+
+def serve_pool(requests: int = SERVE_REQUESTS, pool: int = SERVE_POOL):
+    """(trace, graphs): the request trace and the distinct graphs of its
+    first `pool` requests, the pool the serving benchmark replays."""
+    reqs = serve_requests(requests)
+    graphs = [serve_graph(k, n, m, sd) for (_, k, n, m, sd) in reqs[:min(pool, requests)]]
+    return reqs, graphs
