@@ -6,7 +6,10 @@ Default workload: R-MAT scale 22 (edge factor 16, a,b,c,d = .57,.19,.19,.05,
 counts, CSR resident in HBM before the timed region.  One step = one
 graphlet_count call (prepass, Steps 1-4, result on the host).
 
-Prints one JSON line (the last line of stdout).  Other workloads:
+Prints one JSON line (the last line of stdout).  The default line also
+carries the other two parts of the metric, compact: "batched" (the 8192-graph
+batch, as --workload batch) and "serve" (the Poisson trace, as --workload
+serve); --no-extras leaves them out.  Other workloads:
   --workload er | cl       the other single-graph configurations
   --workload batch         8192 small graphs in one batched call, against one
                            plain call per graph
@@ -37,10 +40,33 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(g, seconds: float, seed: int = 0):
-    """The oracle's per-edge route (|Tri_e|, 4-cliques, induced 4-cycles per
-    edge, literally) on a random sample of the same graph's edges, run for
-    about `seconds` on one host core; edges/s."""
+def host_cpu() -> dict:
+    """This host's CPU model and logical core count (the oracle runs on one)."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
+
+
+def stored_oracle(name: str):
+    """The stored oracle entry of a workload (tests/golden/configs.json)."""
+    path = os.path.join(ROOT, "tests", "golden", "configs.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f).get(name)
+
+
+def per_edge_oracle_rate(g, seconds: float, seed: int = 0):
+    """The oracle's per-edge route (|Tri_e|, 4-cliques, induced 4-cycles of
+    one edge by their definitions) on uniformly sampled edges of the graph,
+    run for about `seconds` on one host core: (edges/s, edges, seconds)."""
     import numpy as np
 
     import oracle
@@ -56,9 +82,33 @@ def cpu_baseline(g, seconds: float, seed: int = 0):
         done += len(idx)
         chunk = min(chunk * 2, 4096)
     dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} uniformly sampled edges of the same graph, per-edge oracle "
-                      f"(|Tri_e|, 4-cliques and induced 4-cycles by definition), {dt:.1f} s"}
+    return done / dt, done, dt
+
+
+def cpu_baseline(g, name: str, seconds: float):
+    """The oracle beside the GPU for a global-count workload.
+
+    value: the identity route (the oracle's global-count route, Chiba-
+    Nishizeki listing plus subset-sum identities), whole graph, one core: its
+    stored time, taken when the stored counts were written (the route needs
+    about an hour on R-MAT scale 22, too long to repeat here; its host is
+    named).  Beside it, measured live on this host for `seconds`: the
+    per-edge route (the literal per-edge definitions) on sampled edges of the
+    same graph."""
+    rate, done, dt = per_edge_oracle_rate(g, seconds)
+    live = {"value": rate, "unit": "edges/s", "cores": 1, "route": "oracle.per_edge",
+            "sample": f"{done} uniformly sampled edges of the same graph, {dt:.1f} s",
+            "host": host_cpu()}
+    st = stored_oracle(name)
+    if st is None or st.get("sha256") != g.sha256() or not st.get("oracle_seconds"):
+        live["kind"] = "oracle"
+        return live
+    return {"value": g.m / st["oracle_seconds"], "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "route": "oracle.identity_route (global counts)",
+            "sample": f"the whole graph, {st['oracle_seconds']} s single-threaded, stored with "
+                      "the oracle's counts of the same CSR",
+            "host": st.get("host", {"cpu_model": "build host, not recorded"}),
+            "per_edge_route_live": live}
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_c4_heavy_bal_rmat22_traffic.md")
@@ -148,7 +198,8 @@ def run_single(args, torch, gl):
         step_ms.append((time.perf_counter() - ts) * 1e3)
         t = gl.graphlet_last_timing()
         for k, v in t.items():
-            phase_sum[k] = phase_sum.get(k, 0) + v
+            if not isinstance(v, list):
+                phase_sum[k] = phase_sum.get(k, 0) + v
         if counts is not None and c != counts:
             raise RuntimeError("counts changed between steps")
         counts = c
@@ -188,9 +239,15 @@ def run_single(args, torch, gl):
                                          "wedges_dense", "dense_hubs", "heavy_items")},
         "counts": [str(x) for x in counts],
     }
+    st = stored_oracle({"rmat22": "rmat", "er": "er", "cl": "cl"}[args.workload])
+    if st is not None and st.get("sha256") == g.sha256():
+        res["matches_oracle"] = [int(x) for x in st["counts"]] == counts
+        if not res["matches_oracle"]:
+            raise SystemExit("counts differ from the stored oracle counts")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle, one core)...")
-        res["cpu_baseline"] = cpu_baseline(g, args.cpu_seconds)
+        res["cpu_baseline"] = cpu_baseline(g, {"rmat22": "rmat", "er": "er", "cl": "cl"}[
+            args.workload], args.cpu_seconds)
     return res
 
 
@@ -245,6 +302,15 @@ def run_batch(args, torch, gl):
         raise SystemExit("batched plan replay differs from the one-shot call")
     ms_dev = plan_device_ms(torch, plan)
     plan.close()
+    matches = None
+    st = stored_oracle("batch8192")
+    if st is not None and st.get("sha256") == b.sha256():
+        import numpy as np
+
+        with np.load(os.path.join(ROOT, "tests", "golden", st["counts_file"])) as z:
+            matches = bool((out.cpu().numpy() == z["counts"]).all())
+        if not matches:
+            raise SystemExit("batched counts differ from the stored oracle counts")
     # baseline: one plain graphlet_count launch per graph, on a sample
     import numpy as np
 
@@ -264,6 +330,20 @@ def run_batch(args, torch, gl):
     per_graph_s = (time.perf_counter() - t1) / len(dev_graphs)
     log(f"[bench] batched {ms:.2f} ms for {b.graphs} graphs; per-graph launches "
         f"{per_graph_s * 1e3:.3f} ms/graph")
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        order = rng.permutation(b.graphs)
+        done, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < args.cpu_seconds / 2 and done < b.graphs:
+            oracle.identity_route(b.graph(int(order[done])))
+            done += 1
+        dt = time.perf_counter() - t0
+        cpu = {"value": done / dt, "unit": "graphs/s", "cores": 1, "kind": "oracle",
+               "route": "oracle.identity_route per graph",
+               "sample": f"{done} uniformly sampled graphs of the batch, {dt:.1f} s",
+               "host": host_cpu()}
     return {
         "metric": "batched graphs/sec", "value": b.graphs / (ms / 1e3), "unit": "graphs/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -277,11 +357,15 @@ def run_batch(args, torch, gl):
                                "sample": f"{len(dev_graphs)} graphs of the batch, one "
                                          "graphlet_count call each, CSR resident"},
         "speedup_vs_per_graph": (b.graphs / (ms / 1e3)) * per_graph_s,
+        "matches_oracle": matches,
+        "cpu_baseline": cpu,
     }
 
 
-def serve_trace(gl, graphs, trace, slots, budget):
-    """Replays (arrival_s, pool index) against a server; returns its stats."""
+def serve_trace(gl, graphs, trace, slots, budget, want=None):
+    """Replays (arrival_s, pool index) against a server; returns its stats.
+    With `want` (the oracle's counts of each pool graph), every result is
+    checked against it."""
     with gl.Server(budget_bytes=budget, slots=slots) as srv:
         t0 = time.perf_counter()
         ids = []
@@ -291,8 +375,10 @@ def serve_trace(gl, graphs, trace, slots, budget):
                 time.sleep(delay)
             g = graphs[gi]
             ids.append(srv.submit(g.n, g.row_ptr, g.col))
-        for i in ids:
-            srv.wait(i)
+        for i, (_, gi) in zip(ids, trace):
+            counts, _ = srv.wait(i)
+            if want is not None and counts != want[gi]:
+                raise SystemExit(f"served counts of pool graph {gi} differ from the oracle's")
         st = srv.stats()
     return st
 
@@ -309,19 +395,23 @@ def run_serve(args, torch, gl):
 
     nreq = args.requests
     pool_n = min(args.pool, nreq)
-    reqs = C.serve_requests(nreq)
     t0 = time.time()
-    graphs = [C.serve_graph(k, n, m, sd) for (_, k, n, m, sd) in reqs[:pool_n]]
+    reqs, graphs = C.serve_pool(nreq, pool_n)
     log(f"[bench] serve pool: {pool_n} graphs, {sum(g.m for g in graphs)} edges "
         f"in {time.time() - t0:.1f}s; {nreq} requests")
     trace = [(reqs[i][0], i % pool_n) for i in range(nreq)]
     budget = 64 << 30
+    want = None
+    st = stored_oracle("serve_pool")
+    if st is not None and len(st["graphs"]) == pool_n and all(
+            g.sha256() == s["sha256"] for g, s in zip(graphs, st["graphs"])):
+        want = [[int(x) for x in s["counts"]] for s in st["graphs"]]
     # warm up the library and the stream-ordered allocator
     serve_trace(gl, graphs, [(0.0, i) for i in range(min(8, pool_n))], 4, budget)
-    served = serve_trace(gl, graphs, trace, 4, budget)
+    served = serve_trace(gl, graphs, trace, 4, budget, want)
     log(f"[bench] served: {served['graphs_per_s']:.1f} graphs/s p50 {served['p50_ms']:.2f} ms "
         f"p99 {served['p99_ms']:.2f} ms")
-    plain = serve_trace(gl, graphs, trace, 1, budget)
+    plain = serve_trace(gl, graphs, trace, 1, budget, want)
     log(f"[bench] per-request plain: {plain['graphs_per_s']:.1f} graphs/s "
         f"p50 {plain['p50_ms']:.2f} ms p99 {plain['p99_ms']:.2f} ms")
     # saturated: every request at time 0
@@ -344,6 +434,7 @@ def run_serve(args, torch, gl):
         "per_request_plain": {k: plain[k] for k in keep},
         "saturated_served": {k: sat[k] for k in keep},
         "saturated_plain": {k: sat1[k] for k in keep},
+        "matches_oracle": want is not None,
     }
 
 
@@ -471,7 +562,8 @@ def run_vertex(args, torch, gl):
     for _ in range(args.steps):
         c, V = gl.graphlet_count_vertex(rp, col, g.n, workspace=ws, out=out)
         for k, v in gl.graphlet_last_timing().items():
-            phase_sum[k] = phase_sum.get(k, 0) + v
+            if not isinstance(v, list):
+                phase_sum[k] = phase_sum.get(k, 0) + v
         if counts is not None and c != counts:
             raise RuntimeError("counts changed between steps")
         counts = c
@@ -575,6 +667,8 @@ def main():
                     help="batch: graphs timed with one plain launch each")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="rmat22: skip the batched and serving parts of the metric")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB device buffer 3 times (known bytes per dispatch, "
                          "to scale hardware byte counters)")
@@ -615,6 +709,20 @@ def main():
         res = run_batch_vertex(args, torch, gl)
     else:
         res = run_single(args, torch, gl)
+        if args.workload == "rmat22" and not args.no_extras:
+            # the other two parts of the metric, compact: batched graphs/s
+            # against per-graph launches, served graphs/s and p50 / p99
+            # against per-request plain launches
+            b = run_batch(args, torch, gl)
+            res["batched"] = {k: b[k] for k in (
+                "metric", "value", "unit", "ms_per_step", "device_ms_per_step",
+                "one_shot_graphs_per_s", "per_graph_launches", "speedup_vs_per_graph",
+                "matches_oracle", "plan", "cpu_baseline")}
+            res["batched"]["config"] = b["config"]
+            sv = run_serve(args, torch, gl)
+            res["serve"] = {k: sv[k] for k in (
+                "metric", "value", "unit", "p50_ms", "p99_ms", "served", "per_request_plain",
+                "saturated_served", "saturated_plain", "matches_oracle", "config")}
     print(json.dumps(res), flush=True)
 
 

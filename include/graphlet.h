@@ -322,6 +322,12 @@ typedef struct gc_timing {
   int64_t heavy_items;       /* work items of phase 4 */
   uint64_t wedges_dense;     /* wedges of the hubs of phase 3 */
   int64_t dense_hubs;        /* hubs counted by phase 3 */
+  /* Vertices u of phase 1 by k = |U(u)|, the neighbours after u in the
+   * degree order (each class is one kernel shape): [0] k <= 64, [1] <= 256,
+   * [2] <= 512, [3] <= 1088, [4] k > 1088 (rows in global memory); [5] the
+   * vertices of [3] with k > 896, whose symmetric rows the per-edge pass
+   * keeps in global memory (with per_edge_out, local or vertex outputs). */
+  int64_t clique_class[6];
 } gc_timing;
 
 void graphlet_timing_enable(int on);
@@ -349,7 +355,10 @@ int graphlet_last_timing(gc_timing *out);
  *                      request failed (its error code; others are unaffected)
  *   gc_server_wait     as poll, blocking until the request ends
  *   gc_server_cancel   a pending request is dropped; a running one finishes
- *                      on the device and its result is discarded
+ *                      on the device and its result is discarded (a running
+ *                      update is then not applied: the graph and its counts
+ *                      stay as they were).  Either way the request ends
+ *                      CANCELLED, unless it had already finished.
  *   gc_server_release  forgets a finished request (its id becomes invalid)
  *   gc_server_stats    counters, latency percentiles over completed requests
  *                      and throughput since creation or the last reset

@@ -114,7 +114,7 @@ class _Timing(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 8), ("clique_entries", ctypes.c_uint64),
                 ("wedges_light", ctypes.c_uint64), ("wedges_heavy", ctypes.c_uint64),
                 ("heavy_items", ctypes.c_int64), ("wedges_dense", ctypes.c_uint64),
-                ("dense_hubs", ctypes.c_int64)]
+                ("dense_hubs", ctypes.c_int64), ("clique_class", ctypes.c_int64 * 6)]
 
 
 def load():
@@ -498,7 +498,8 @@ def graphlet_last_timing() -> dict:
     d = {f"{p}_ms": float(t.ms[i]) for i, p in enumerate(PHASES)}
     d.update(clique_entries=int(t.clique_entries), wedges_light=int(t.wedges_light),
              wedges_heavy=int(t.wedges_heavy), heavy_items=int(t.heavy_items),
-             wedges_dense=int(t.wedges_dense), dense_hubs=int(t.dense_hubs))
+             wedges_dense=int(t.wedges_dense), dense_hubs=int(t.dense_hubs),
+             clique_class=[int(x) for x in t.clique_class])
     return d
 
 

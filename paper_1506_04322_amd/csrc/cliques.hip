@@ -534,10 +534,6 @@ __global__ __launch_bounds__(BLOCK) void k_tk_global(TkArgs g) {
 
 }  // namespace
 
-// Largest k of the per-edge 1024-thread class whose symmetric rows stay in LDS.
-constexpr int kTkPeLds = 896;
-static_assert(kTkLim2 < kTkPeLds && kTkPeLds < kTkLim3, "splits the 1024-thread class");
-
 int launch_cliques(TkArgs g, int bin, bool per_edge, hipStream_t s) {
   if (g.nlist <= 0) return GC_OK;
   auto grid = [&](int cap) { return (unsigned)std::min(g.nlist, cap); };

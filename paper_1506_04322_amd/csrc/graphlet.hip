@@ -599,6 +599,8 @@ int run(const gc_csr *G, gc_u128 out17[17], int64_t *per_edge_out, int64_t *loca
     t.heavy_items = h.nitems;
     t.wedges_dense = dense_wedges;
     t.dense_hubs = ndense;
+    for (int b = 0; b < kTkBins; b++) t.clique_class[b] = hc.tk_cnt[b];
+    t.clique_class[kTkBins] = hc.tk_pe_global;
   }
   u128 A[kAcc];
   for (int i = 0; i < kAcc; i++) A[i] = ((u128)h.step3[i][1] << 64) | h.step3[i][0];

@@ -29,6 +29,10 @@ enum AccIdx {
 // Size classes of the clique pass by k = |U(u)|.
 constexpr int kTkBins = 5;
 constexpr int kTkLim0 = 64, kTkLim1 = 256, kTkLim2 = 512, kTkLim3 = 1088;
+// Largest k of the per-edge 1024-thread class whose symmetric rows stay in
+// LDS; the class's larger vertices keep their rows in a global slot.
+constexpr int kTkPeLds = 896;
+static_assert(kTkLim2 < kTkPeLds && kTkPeLds < kTkLim3, "splits the 1024-thread class");
 // Class of a vertex with k = |U(u)| >= 2 upper neighbours.
 __host__ __device__ inline int tk_class(int k) {
   return k <= kTkLim0 ? 0 : k <= kTkLim1 ? 1 : k <= kTkLim2 ? 2 : k <= kTkLim3 ? 3 : 4;
@@ -83,7 +87,8 @@ struct Counters {
   int32_t max_lcnt_heavy;
   int32_t max_deg;
   int32_t c4_medium;
-  int32_t pad[5];
+  int32_t tk_pe_global;  // vertices with kTkPeLds < k <= kTkLim3
+  int32_t pad[4];
   u64 wedges_light;
   u64 wedges_heavy;
   u64 clique_entries;

@@ -207,6 +207,8 @@ __global__ __launch_bounds__(256) void k_bins(const int32_t *ucnt, const int32_t
   wave_append(cls == 2, x, tk2, &cnt->tk_cnt[2]);
   wave_append(cls == 3, x, tk3, &cnt->tk_cnt[3]);
   wave_append(cls == 4, x, tk4, &cnt->tk_cnt[4]);
+  const u64 gslot = __ballot(cls == 3 && k > kTkPeLds);
+  if (lane_id() == 0 && gslot) atomicAdd(&cnt->tk_pe_global, __popcll(gslot));
   const bool light = w >= 2 && w <= kLightWedges;  // one wedge cannot close a cycle
   const bool medium = w > kLightWedges && w <= medium_max;
   const bool heavy = w > medium_max && w > kLightWedges;

@@ -228,11 +228,16 @@ void run_update(gc_server *S, Request *r, hipStream_t st) {
     }
   }
   if (rc == GC_OK) {
+    // A request cancelled while it ran is not committed: the spare buffer it
+    // wrote is scratch until the swap, so graph and counts stay as they were
+    // and the request ends CANCELLED.
     std::lock_guard<std::mutex> lk(S->mu);
-    G->live = 1 - G->live;
-    G->nnz += r->insert ? 2 : -2;
-    std::memcpy(G->counts, c, sizeof(c));
-    std::memcpy(r->out, c, sizeof(c));
+    if (!r->cancel) {
+      G->live = 1 - G->live;
+      G->nnz += r->insert ? 2 : -2;
+      std::memcpy(G->counts, c, sizeof(c));
+      std::memcpy(r->out, c, sizeof(c));
+    }
   }
   finish(S, r, rc, err, 0);
 }

@@ -4,6 +4,7 @@ All counts are integers, so the bar is bit-exact equality everywhere: the
 17-vector (Table 1 classes) and the per-edge |Tri_e|, 4-clique and induced
 4-cycle counts in canonical edge order.
 """
+import hashlib
 import json
 import os
 from math import comb
@@ -85,61 +86,110 @@ def test_isolated_vertices_many():
     check_full(g)
 
 
+def clique_classes(g, per_edge):
+    """Runs the graph with timing on; returns the vertex counts per clique
+    kernel class (gc_timing.clique_class) and the results."""
+    gl.graphlet_timing_enable(True)
+    try:
+        res = gpu_counts(g, per_edge=per_edge, validate=False)
+        return gl.graphlet_last_timing()["clique_class"], res
+    finally:
+        gl.graphlet_timing_enable(False)
+
+
 def test_complete_graphs_cover_every_clique_bin():
-    # K_n: |U(u)| runs up to n-1, so n = 700 reaches the global-memory class
-    for n in (4, 65, 300, 700):
+    # K_n: |U(u)| takes every value 0 .. n-1, so K_n runs every clique class
+    # with a bound below n: k <= 64, 256, 512, 1088 in LDS; in per-edge mode
+    # 896 < k <= 1088 keeps its rows in a global slot; k > 1088 runs the
+    # global-memory kernel in both modes
+    for n in (4, 65, 300, 700, 1000, 1100):
         edges = [(a, b) for a in range(n) for b in range(a + 1, n)]
         g = graphgen.from_edges(n, edges)
-        got, pe = gpu_counts(g, per_edge=True)
+        cls, got = clique_classes(g, per_edge=False)
         want = [0] * 17
         want[0], want[2], want[6] = comb(n, 2), comb(n, 3), comb(n, 4)
         assert got == want
+        cls2, (got2, pe) = clique_classes(g, per_edge=True)
+        assert got2 == want and cls2 == cls
         assert (pe[0] == n - 2).all() and (pe[1] == comb(n - 2, 2)).all() and (pe[2] == 0).all()
+        # vertex of rank r has k = n - 1 - r upper neighbours
+        ks = np.arange(n - 1, -1, -1)
+        ks = ks[ks >= 2]
+        assert cls[0] == int(((ks >= 2) & (ks <= 64)).sum())
+        assert cls[1] == int(((ks > 64) & (ks <= 256)).sum())
+        assert cls[2] == int(((ks > 256) & (ks <= 512)).sum())
+        assert cls[3] == int(((ks > 512) & (ks <= 1088)).sum())
+        assert cls[4] == int((ks > 1088).sum())
+        assert cls[5] == int(((ks > 896) & (ks <= 1088)).sum())
+    assert cls[4] > 0 and cls[5] > 0  # K_1100 ran both global-memory shapes
 
 
-def test_complete_bipartite_heavy_cycles():
-    a, b = 300, 400
-    g = graphgen.from_edges(a + b, [(i, a + j) for i in range(a) for j in range(b)])
-    got, pe = gpu_counts(g, per_edge=True)
-    assert got == oracle.identity_route(g)
-    assert got[9] == comb(a, 2) * comb(b, 2)
-    assert (pe[0] == 0).all() and (pe[1] == 0).all() and (pe[2] == (a - 1) * (b - 1)).all()
+def hub_core_graph(na=1150, nb=1500, nc=400, pa=0.05, periphery=2000, seed=61):
+    """Vertices with more than 1088 upper neighbours, at moderate clique
+    counts: a set A (sparse inside, p = pa) that every vertex of C and a
+    fraction q_b ~ U[0.02, 0.98] of B attach to, plus a sparse periphery.
+    A has the highest degrees, so the upper neighbours of a vertex of C are
+    all of A (k = 1150 > 1088) and those of b in B about q_b |A|, which
+    spans every clique class, the per-edge global-slot one (896 < k <= 1088)
+    included."""
+    rng = np.random.default_rng(seed)
+    A = np.arange(na)
+    n = na + nb + nc + periphery
+    iu = np.triu_indices(na, 1)
+    keep = rng.random(len(iu[0])) < pa
+    edges = list(zip(iu[0][keep].tolist(), iu[1][keep].tolist()))
+    q = rng.uniform(0.02, 0.98, nb)
+    for i in range(nb):
+        b = na + i
+        edges += [(int(a), b) for a in A[rng.random(na) < q[i]]]
+    for i in range(nc):
+        c = na + nb + i
+        edges += [(int(a), c) for a in A]
+    for x in range(na + nb + nc, n):
+        for y in rng.integers(0, n, 3):
+            if int(y) != x:
+                edges.append((min(x, int(y)), max(x, int(y))))
+    return graphgen.from_edges(n, edges)
 
 
-def test_star_and_hub_hub():
-    g = graphgen.from_edges(5001, [(0, i) for i in range(1, 5001)])
-    check_full(g)
-    rng = np.random.default_rng(5)
-    edges = [(0, 1)] + [(0, i) for i in range(2, 3000)] + [(1, i) for i in range(2, 3000, 2)]
-    edges += [tuple(rng.integers(2, 3000, 2)) for _ in range(4000)]
-    check_full(graphgen.from_edges(3000, edges))
-
-
-def test_dense_random_heavy_paths():
-    rng = np.random.default_rng(9)
-    check_full(rand_graph(rng, 400, 0.35))
-    check_full(rand_graph(rng, 900, 0.05))
-
-
-def test_powerlaw_and_rmat_medium():
-    check_full(graphgen.chung_lu(20000, 2.1, 4.0, 120000, 11))
-    check_full(graphgen.rmat(13, 16, 0.57, 0.19, 0.19, 12))
-
-
-def test_rgg_and_er_medium():
-    check_full(graphgen.rgg_torus(3000, 12.0, 13))
-    check_full(graphgen.er_gnm(5000, 60000, 14))
-
-
-def test_run_to_run_identical_and_relabelled():
-    g = graphgen.rmat(12, 16, 0.57, 0.19, 0.19, 21)
-    a = gpu_counts(g, per_edge=True)
-    b = gpu_counts(g, per_edge=True)
-    assert a[0] == b[0] and (a[1] == b[1]).all()
-    perm = np.random.default_rng(3).permutation(g.n)
+def test_hub_core_every_clique_class_vs_oracle():
+    g = hub_core_graph()
+    want = oracle.identity_route(g)
+    cls, got = clique_classes(g, per_edge=False)
+    assert got == want
+    cls2, (got2, pe) = clique_classes(g, per_edge=True)
+    assert got2 == want
+    assert all(c > 0 for c in cls), cls  # every class, both global-memory shapes
+    assert int(pe[0].sum()) == 3 * want[2]
+    assert int(pe[1].sum()) == 6 * want[6]
+    assert int(pe[2].sum()) == 4 * want[9]
+    # per-edge values against the literal per-edge oracle: edges at vertices
+    # of the k > 1088 class (C), at vertices of the global-slot class
+    # (b in B with 896 < k <= 1088), random edges, periphery edges
     eu, ev = oracle.edges(g)
-    h = graphgen.from_edges(g.n, list(zip(perm[eu], perm[ev])))
-    assert gpu_counts(h) == a[0]
+    na, nb, nc = 1150, 1500, 400
+    d = g.degrees()
+    lo_end = np.maximum(eu, ev)  # the B, C or periphery end of an edge
+    in_c = (lo_end >= na + nb) & (lo_end < na + nb + nc)
+    in_b = (lo_end >= na) & (lo_end < na + nb)
+    gslot = in_b & (d[lo_end] > 930) & (d[lo_end] < 1080)
+    per = lo_end >= na + nb + nc
+    rng = np.random.default_rng(62)
+    idx = np.unique(np.concatenate([
+        rng.choice(np.nonzero(in_c)[0], 40, replace=False),
+        rng.choice(np.nonzero(gslot)[0], 40, replace=False),
+        rng.choice(len(eu), 60, replace=False),
+        rng.choice(np.nonzero(per)[0], 40, replace=False)]))
+    T, K4, C4 = oracle.per_edge(g, eu[idx], ev[idx])
+    np.testing.assert_array_equal(pe[0][idx], T)
+    np.testing.assert_array_equal(pe[1][idx], K4)
+    np.testing.assert_array_equal(pe[2][idx], C4)
+    # local vectors through the same classes
+    counts, L = gpu_local(g)
+    assert counts == want
+    check_local_sums(g, counts, L)
+    sub = idx[rng.choice(len(idx), 60, replace=False)]
+    np.testing.assert_array_equal(L[sub], oracle.edge_local(g, eu[sub], ev[sub]))
 
 
 # ------------------------------------------------------------ configurations
@@ -223,7 +273,14 @@ def test_config3_rmat22_per_edge_sampled():
     d = g.degrees()
     rng = np.random.default_rng(57)
     cheap = np.nonzero(d[eu] + d[ev] < 3000)[0]
-    idx = np.unique(rng.choice(cheap, 400, replace=False))
+    idx = rng.choice(cheap, 400, replace=False)
+    # edges at the hubs (the heavy 4-cycle items, the dense-slab vertices and
+    # the global-slot clique class run there) whose other end has low degree:
+    # the literal oracle walks the small star side, so they stay cheap
+    hubs = np.argsort(-d, kind="stable")[:40]
+    lo_end = np.where(np.isin(eu, hubs), ev, eu)
+    at_hub = np.nonzero((np.isin(eu, hubs) | np.isin(ev, hubs)) & (d[lo_end] <= 12))[0]
+    idx = np.unique(np.concatenate([idx, rng.choice(at_hub, 120, replace=False)]))
     T, K4, C4 = oracle.per_edge(g, eu[idx], ev[idx])
     np.testing.assert_array_equal(pe[0][idx], T)
     np.testing.assert_array_equal(pe[1][idx], K4)
@@ -602,17 +659,38 @@ def test_batched_mixed_sizes_vs_oracle():
         assert out[i].tolist() == oracle.identity_route(g), i
 
 
-def test_batched_config4_sample():
+def batch8192_oracle_counts(b):
+    """The oracle's counts of every graph of the 8192-graph batch, stored by
+    tests/golden/make_golden.py (identity route, one graph at a time)."""
+    gd = golden("batch8192")
+    assert gd is not None, "batch8192 oracle counts not generated"
+    assert gd["sha256"] == b.sha256() and gd["graphs"] == b.graphs
+    with np.load(os.path.join(HERE, "golden", gd["counts_file"])) as z:
+        want = z["counts"]
+    h = hashlib.sha256(np.ascontiguousarray(want, dtype="<i8").tobytes()).hexdigest()
+    assert h == gd["counts_sha256"]
+    return want
+
+
+def test_batched_config4_every_graph_vs_oracle():
+    # all 8192 x 17 entries, for the one-shot call and for the autotuned plan
+    # replayed as a HIP graph (the form the benchmark times)
     b = C.batch8192()
-    out = batched_gpu(b)
+    want = batch8192_oracle_counts(b)
+    # spot check: the stored matrix is the oracle's
     rng = np.random.default_rng(4)
-    for i in rng.choice(b.graphs, 120, replace=False):
-        g = b.graph(int(i))
-        assert out[i].tolist() == oracle.identity_route(g), i
-    # every row is a complete census of its graph
-    n = np.diff(b.node_off)
-    assert (out[:, 2:6].sum(1) == n * (n - 1) * (n - 2) // 6).all()
-    assert (out[:, 6:].sum(1) == n * (n - 1) * (n - 2) * (n - 3) // 24).all()
+    for i in rng.choice(b.graphs, 8, replace=False):
+        assert want[i].tolist() == oracle.identity_route(b.graph(int(i))), i
+    nd, rp, col = dev(b.node_off), dev(b.row_ptr), dev(b.col)
+    out = gl.graphlet_count_batched(nd, rp, col).cpu().numpy()
+    bad = np.nonzero((out != want).any(1))[0]
+    assert len(bad) == 0, f"{len(bad)} graphs differ, first {bad[:10].tolist()}"
+    with gl.BatchPlan(nd, rp, col, tune=True) as plan:
+        for rep in range(2):
+            plan.out.zero_()
+            got = plan.run().cpu().numpy()
+            bad = np.nonzero((got != want).any(1))[0]
+            assert len(bad) == 0, f"replay {rep}: {len(bad)} graphs differ, first {bad[:10]}"
 
 
 def test_batched_equals_single_graph_path():

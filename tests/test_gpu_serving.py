@@ -238,3 +238,84 @@ def test_cancelled_registration_cancels_its_updates():
         srv.wait(busy)
         srv.unregister(gid)
         assert srv.stats()["cancelled"] >= 2
+
+
+def test_cancelled_update_is_applied_only_if_it_finished():
+    # an update cancelled right after its submission ends either CANCELLED
+    # (pending or running: the graph and its counts are as before) or DONE
+    # (it finished first: the change is applied); never half of each
+    g = graphgen.rmat(14, 16, 0.57, 0.19, 0.19, 8)
+    d = g.degrees()
+    hub = int(np.argmax(d))
+    eu, ev = oracle.edges(g)
+    sel = np.nonzero((eu == hub) | (ev == hub))[0][:12]
+    with gl.Server(budget_bytes=8 << 30, slots=1) as srv:
+        gid = srv.register(g.n, g.row_ptr, g.col)
+        counts, _ = srv.wait(gid)
+        outcomes = set()
+        for k in sel:
+            a, b = int(eu[k]), int(ev[k])
+            rid = srv.update(gid, a, b, False)
+            srv.cancel(rid)
+            try:
+                after, _ = srv.wait(rid)
+                outcomes.add("done")
+                assert srv.graph_counts(gid) == after
+                counts = gl.graphlet_update_edge(dev(g.row_ptr), dev(g.col), g.n, a, b, False,
+                                                 counts)
+                assert after == counts
+                g, _ = _toggle_edge(g, a, b)
+            except gl.GraphletError:
+                outcomes.add("cancelled")
+                assert srv.graph_counts(gid) == counts
+        # the kept graph is still consistent: one more update applies cleanly
+        a, b = int(eu[sel[-1]]), int(ev[sel[-1]])
+        present = b in set(g.col[g.row_ptr[a]:g.row_ptr[a + 1]].tolist())
+        got, _ = srv.wait(srv.update(gid, a, b, not present))
+        g2, _ = _toggle_edge(g, a, b)
+        assert got == standalone(g2)
+        srv.unregister(gid)
+    assert outcomes
+
+
+def _toggle_edge(g, a, b):
+    eu, ev = oracle.edges(g)
+    edges = set(zip(eu.tolist(), ev.tolist()))
+    key = (min(a, b), max(a, b))
+    present = key in edges
+    (edges.discard if present else edges.add)(key)
+    return graphgen.from_edges(g.n, sorted(edges)), not present
+
+
+def serve_pool_oracle_counts(graphs):
+    """The oracle's counts of the serving benchmark's pool of graphs, stored
+    by tests/golden/make_golden.py."""
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "configs.json")
+    with open(path) as f:
+        gd = json.load(f)["serve_pool"]["graphs"]
+    assert len(gd) == len(graphs)
+    for g, want in zip(graphs, gd):
+        assert g.sha256() == want["sha256"] and g.m == want["m"]
+    return [[int(x) for x in want["counts"]] for want in gd]
+
+
+def test_serve_pool_every_result_vs_oracle():
+    # the benchmark's 96 graphs (1e3 to 2e6 edges, Chung-Lu and ER), all
+    # submitted at once through 4 slots so that they overlap on the device,
+    # then again one at a time: every result equals the oracle's counts
+    _, graphs = C.serve_pool()
+    want = serve_pool_oracle_counts(graphs)
+    for slots, burst in ((4, True), (1, False)):
+        with gl.Server(budget_bytes=64 << 30, slots=slots) as srv:
+            if burst:
+                ids = [srv.submit(g.n, g.row_ptr, g.col) for g in graphs]
+                got = [srv.wait(i)[0] for i in ids]
+            else:
+                got = [srv.wait(srv.submit(g.n, g.row_ptr, g.col))[0] for g in graphs]
+            st = srv.stats()
+        assert st["completed"] == len(graphs) and st["failed"] == 0
+        for i, (a, b) in enumerate(zip(got, want)):
+            assert a == b, (slots, i)
