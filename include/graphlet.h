@@ -212,6 +212,26 @@ typedef struct gc_batch {
 int graphlet_count_batched(const gc_batch *b, int64_t *out, void *stream, uint32_t flags);
 
 /*
+ * graphlet_count_batched without any device allocation, for callers that
+ * cannot allocate device memory (serving loops with a fixed footprint,
+ * harnesses that forbid hipMalloc).  Same arguments, checks, results and
+ * errors as graphlet_count_batched, with the size classes and order it would
+ * use; it allocates nothing (no hipMalloc, hipMallocAsync or library
+ * allocator).  Its scratch (an error word, the per-graph sizes and the class
+ * lists: about 1.3 MB) is a static device array of the library that each GPU
+ * it runs on holds until the process ends, so a batch holds at most
+ * GC_NOALLOC_MAX_GRAPHS graphs: a larger one is refused with GC_EINVAL before
+ * any device work.  Every call on a device shares that device's array, which
+ * keeps the last call's contents (the call clears what must start at zero);
+ * the library makes calls on one device from several host threads take turns
+ * (a lock per device), since calls that overlapped on one array would race.
+ * Stream-ordered; returns when the results are complete.
+ */
+#define GC_NOALLOC_MAX_GRAPHS 65536
+int graphlet_count_batched_noalloc(const gc_batch *b, int64_t *out, void *stream,
+                                   uint32_t flags);
+
+/*
  * Per-vertex counts of every graph of a batch (the node-level view of the
  * per-edge local counts of Section 4.2, for the graph-classification batches
  * of Section 6): for each vertex v of each graph and each of the 17 classes,

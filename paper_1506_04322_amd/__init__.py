@@ -31,6 +31,7 @@ ERRORS = {
     -5: "GC_EOVERFLOW", -6: "GC_ENOMEM", -7: "GC_EHIP", -8: "GC_EINTERNAL",
 }
 BATCH_MAX_N = 1024
+NOALLOC_MAX_GRAPHS = 65536
 
 
 class GraphletError(RuntimeError):
@@ -63,6 +64,7 @@ EXPORTS = [
     "graphlet_count_vertex",
     "graphlet_update_edge",
     "graphlet_count_batched",
+    "graphlet_count_batched_noalloc",
     "graphlet_batch_vertex",
     "graphlet_batch_gfd",
     "graphlet_batch_plan_create",
@@ -144,6 +146,8 @@ def load():
     lib.graphlet_batch_gfd.restype = ctypes.c_int
     lib.graphlet_count_batched.argtypes = [ctypes.POINTER(_Batch), P, P, ctypes.c_uint32]
     lib.graphlet_count_batched.restype = ctypes.c_int
+    lib.graphlet_count_batched_noalloc.argtypes = [ctypes.POINTER(_Batch), P, P, ctypes.c_uint32]
+    lib.graphlet_count_batched_noalloc.restype = ctypes.c_int
     lib.graphlet_batch_vertex.argtypes = [ctypes.POINTER(_Batch), P, P, ctypes.c_uint32]
     lib.graphlet_batch_vertex.restype = ctypes.c_int
     lib.graphlet_batch_plan_create.argtypes = [ctypes.POINTER(_Batch), P, ctypes.c_int, P,
@@ -368,6 +372,28 @@ def graphlet_count_batched(node_off, row_ptr, col, out=None, stream=None, valida
     if rc != 0:
         raise GraphletError(rc, graphlet_last_error())
     return out[:G]
+
+
+def graphlet_count_batched_noalloc(node_off, row_ptr, col, out, stream=None, validate=False):
+    """graphlet_count_batched into the caller's [G, 17] int64 device tensor
+    `out`, through the entry point that allocates no device memory (at most
+    NOALLOC_MAX_GRAPHS graphs)."""
+    import torch
+
+    lib = load()
+    _check_dev(node_off, torch.int64, "node_off")
+    _check_dev(row_ptr, torch.int32, "row_ptr")
+    _check_dev(col, torch.int32, "col")
+    _check_dev(out, torch.int64, "out")
+    G = node_off.numel() - 1
+    if out.numel() < 17 * G:
+        raise ValueError("out too small")
+    b = _Batch(G, node_off.data_ptr(), row_ptr.data_ptr(), col.data_ptr() if col.numel() else 0)
+    rc = lib.graphlet_count_batched_noalloc(ctypes.byref(b), out.data_ptr(), _stream_ptr(stream),
+                                            GC_VALIDATE if validate else 0)
+    if rc != 0:
+        raise GraphletError(rc, graphlet_last_error())
+    return out.view(-1)[:17 * G].view(G, 17)
 
 
 def graphlet_batch_vertex(node_off, row_ptr, col, out=None, stream=None, validate=False):

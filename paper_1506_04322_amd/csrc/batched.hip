@@ -336,6 +336,7 @@ struct gc_batch_plan {
   int32_t *herr = nullptr;     // pinned (plans), or &hval (one-shot calls)
   int32_t hval = 0;
   bool stream_owned = false;   // dbuf from hipMallocAsync on the call's stream
+  bool borrowed = false;       // dbuf is the caller's (not freed with the plan)
   hipStream_t owner = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -534,7 +535,7 @@ int time_plan(gc_batch_plan *p, hipStream_t s, double *ms) {
 // returns, per graph, its vertex count and its adjacency-list length.  Shared
 // with the batched per-vertex entry point.
 int check_batch(const gc_batch *b, int64_t *out, hipStream_t s, uint32_t flags,
-                std::vector<int64_t> *sizes) {
+                std::vector<int64_t> *sizes, int32_t *err_buf, int64_t *sizes_buf) {
   if (!b || b->graphs < 0 || b->graphs > (1ll << 30) ||
       (b->graphs > 0 && (!b->node_off || !b->row_ptr || !out))) {
     set_error("invalid batch arguments");
@@ -543,12 +544,20 @@ int check_batch(const gc_batch *b, int64_t *out, hipStream_t s, uint32_t flags,
   const int64_t G = b->graphs;
   sizes->assign(2 * G, 0);
   if (G == 0) return GC_OK;
-  int32_t *err = nullptr;
-  int64_t *dsz = nullptr;
-  GC_TRY_HIP(hipMallocAsync((void **)&err, 4, s));
-  hipError_t e = hipMallocAsync((void **)&dsz, sizeof(int64_t) * 2 * G, s);
+  // the caller's buffers (the allocation-free entry point), else stream-ordered ones
+  const bool own = err_buf == nullptr;
+  int32_t *err = err_buf;
+  int64_t *dsz = sizes_buf;
+  hipError_t e = hipSuccess;
+  if (own) {
+    GC_TRY_HIP(hipMallocAsync((void **)&err, 4, s));
+    e = hipMallocAsync((void **)&dsz, sizeof(int64_t) * 2 * G, s);
+  }
   int32_t h = 0;
-  if (e == hipSuccess) e = hipMemcpyAsync(err, &h, 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    k_batch_reset<<<1, 64, 0, s>>>(err);
+    e = hipGetLastError();
+  }
   if (e == hipSuccess) {
     const unsigned grid = (unsigned)((G + 255) / 256);
     k_batch_check<<<grid, 256, 0, s>>>(b->node_off, b->row_ptr, b->col, G,
@@ -559,8 +568,10 @@ int check_batch(const gc_batch *b, int64_t *out, hipStream_t s, uint32_t flags,
   if (e == hipSuccess) e = hipMemcpyAsync(&h, err, 4, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(sizes->data(), dsz, sizeof(int64_t) * 2 * G, hipMemcpyDeviceToHost, s);
-  if (dsz) (void)hipFreeAsync(dsz, s);
-  (void)hipFreeAsync(err, s);
+  if (own) {
+    if (dsz) (void)hipFreeAsync(dsz, s);
+    (void)hipFreeAsync(err, s);
+  }
   hipError_t f = hipStreamSynchronize(s);
   if (e == hipSuccess) e = f;
   if (e != hipSuccess) {
@@ -580,7 +591,9 @@ namespace {
 void destroy_plan(gc_batch_plan *p) {
   if (!p) return;
   drop_graph(p);
-  if (p->stream_owned) {
+  if (p->borrowed) {
+    // nothing of the plan's own on the device
+  } else if (p->stream_owned) {
     if (p->dbuf) (void)hipFreeAsync(p->dbuf, p->owner);
   } else {
     if (p->dbuf) (void)hipFree(p->dbuf);
@@ -613,15 +626,23 @@ BatchShape default_shape(int mw) {
   return BatchShape{256, (0x24u & (topbit - 1)) | topbit};
 }
 
+// Device buffers a call brings in instead of allocating: the error word, the
+// per-graph sizes (2 G int64) and the class lists (G + 8 int32).
+struct BatchScratch {
+  int32_t *err;
+  int64_t *sizes;
+  int32_t *dbuf;
+};
+
 int create_plan(const gc_batch *b, int64_t *out, int tune, bool capture, hipStream_t s,
-                uint32_t flags, gc_batch_plan **result) {
+                uint32_t flags, gc_batch_plan **result, const BatchScratch *bs = nullptr) {
   if (!result) {
     set_error("null plan pointer");
     return GC_EINVAL;
   }
   *result = nullptr;
   std::vector<int64_t> sizes;
-  GC_TRY(check_batch(b, out, s, flags, &sizes));
+  GC_TRY(check_batch(b, out, s, flags, &sizes, bs ? bs->err : nullptr, bs ? bs->sizes : nullptr));
   gc_batch_plan *p = new (std::nothrow) gc_batch_plan();
   if (!p) return GC_ENOMEM;
   p->b = *b;
@@ -629,7 +650,12 @@ int create_plan(const gc_batch *b, int64_t *out, int tune, bool capture, hipStre
   p->sizes.swap(sizes);
   const int64_t G = b->graphs;
   hipError_t e;
-  if (capture) {
+  if (bs) {  // one call on the caller's scratch: nothing allocated
+    p->borrowed = true;
+    p->herr = &p->hval;
+    p->dbuf = bs->dbuf;
+    e = hipSuccess;
+  } else if (capture) {
     e = hipMalloc((void **)&p->dbuf, sizeof(int32_t) * (G + 8));
     if (e == hipSuccess) e = hipHostMalloc((void **)&p->herr, 64, hipHostMallocDefault);
   } else {  // one call: stream-ordered scratch, freed when the call ends
@@ -704,6 +730,29 @@ int create_plan(const gc_batch *b, int64_t *out, int tune, bool capture, hipStre
 }  // namespace
 }  // namespace gc
 
+// Scratch of graphlet_count_batched_noalloc, one copy per device (each GPU the
+// library runs on holds it until the process ends): the error word (padded to
+// 256 bytes), then (n, nnz) of each graph, then the class-ordered graph list.
+constexpr size_t kNaErrBytes = 256;
+constexpr size_t kNaSizesBytes = sizeof(int64_t) * 2 * GC_NOALLOC_MAX_GRAPHS;
+constexpr size_t kNaListBytes = sizeof(int32_t) * (GC_NOALLOC_MAX_GRAPHS + 8);
+constexpr size_t kNaBytes = kNaErrBytes + kNaSizesBytes + kNaListBytes;
+static_assert(kNaSizesBytes % 256 == 0, "list stays aligned");
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+namespace gc {
+namespace {
+
+constexpr int kNaMaxDevices = 64;
+// Per device: the device address of `scratch` (host code never uses the
+// array's own name, a host-side stand-in) and the lock that makes calls on
+// that device take turns with the array.
+unsigned char *g_na_ptr[kNaMaxDevices];
+std::mutex g_na_mu[kNaMaxDevices];
+
+}  // namespace
+}  // namespace gc
+
 extern "C" {
 
 int graphlet_batch_plan_create(const gc_batch *b, int64_t *out, int tune, void *stream,
@@ -756,7 +805,7 @@ int graphlet_batch_plan_reshape(gc_batch_plan *p, int block, uint32_t class_word
   if (p->b.graphs == 0) return GC_OK;
   try {
     // the batch may hold new graphs of other sizes: re-read them
-    int rc = gc::check_batch(&p->b, p->out, (hipStream_t)stream, 0, &p->sizes);
+    int rc = gc::check_batch(&p->b, p->out, (hipStream_t)stream, 0, &p->sizes, nullptr, nullptr);
     if (rc != GC_OK) return rc;
     unsigned cls = 0;
     for (int k = 0; k < gc::kNumWords; k++)
@@ -802,6 +851,59 @@ int graphlet_count_batched(const gc_batch *b, int64_t *out, void *stream, uint32
     int rc = gc::create_plan(b, out, 0, false, (hipStream_t)stream, flags, &p);
     if (rc != GC_OK) return rc;
     rc = gc::run_plan(p, (hipStream_t)stream);
+    gc::destroy_plan(p);
+    return rc;
+  } catch (...) {
+    gc::set_error("unexpected exception");
+    return GC_EINTERNAL;
+  }
+}
+
+
+int graphlet_count_batched_noalloc(const gc_batch *b, int64_t *out, void *stream,
+                                   uint32_t flags) {
+  gc::clear_error();
+  if (!b) {
+    gc::set_error("invalid batch arguments");
+    return GC_EINVAL;
+  }
+  if (b->graphs > GC_NOALLOC_MAX_GRAPHS) {
+    gc::set_error("batch of %lld graphs exceeds the allocation-free limit of %d graphs",
+                  (long long)b->graphs, GC_NOALLOC_MAX_GRAPHS);
+    return GC_EINVAL;
+  }
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    gc::set_error("hipGetDevice: %s", hipGetErrorString(e));
+    return GC_EHIP;
+  }
+  if (dev < 0 || dev >= gc::kNaMaxDevices) {
+    gc::set_error("device %d beyond the allocation-free entry point's %d devices", dev,
+                  gc::kNaMaxDevices);
+    return GC_EINVAL;
+  }
+  try {
+    std::lock_guard<std::mutex> lk(gc::g_na_mu[dev]);
+    if (!gc::g_na_ptr[dev]) {  // first call on this device, which is current
+      unsigned char *ptr = nullptr;
+      e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr) {
+        gc::set_error("hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        return GC_EHIP;
+      }
+      gc::g_na_ptr[dev] = ptr;
+    }
+    unsigned char *base = gc::g_na_ptr[dev];
+    gc::BatchScratch bs;
+    bs.err = reinterpret_cast<int32_t *>(base);
+    bs.sizes = reinterpret_cast<int64_t *>(base + kNaErrBytes);
+    bs.dbuf = reinterpret_cast<int32_t *>(base + kNaErrBytes + kNaSizesBytes);
+    const hipStream_t s = (hipStream_t)stream;
+    gc_batch_plan *p = nullptr;
+    int rc = gc::create_plan(b, out, 0, false, s, flags, &p, &bs);
+    if (rc != GC_OK) return rc;
+    rc = gc::run_plan(p, s);
     gc::destroy_plan(p);
     return rc;
   } catch (...) {

@@ -43,7 +43,7 @@
 namespace gc {
 
 int check_batch(const gc_batch *b, int64_t *out, hipStream_t s, uint32_t flags,
-                std::vector<int64_t> *sizes);
+                std::vector<int64_t> *sizes, int32_t *err_buf, int64_t *sizes_buf);
 
 namespace {
 
@@ -314,7 +314,8 @@ extern "C" int graphlet_batch_vertex(const gc_batch *b, uint64_t *out, void *str
     hipStream_t s = (hipStream_t)stream;
     std::vector<int64_t> sizes;
     // the validation, the size check (GC_BATCH_MAX_N) and the sizes
-    int rc = gc::check_batch(b, reinterpret_cast<int64_t *>(out), s, flags, &sizes);
+    int rc = gc::check_batch(b, reinterpret_cast<int64_t *>(out), s, flags, &sizes, nullptr,
+                             nullptr);
     if (rc != GC_OK) return rc;
     const int64_t G = b->graphs;
     // bin the graphs with vertices by row width, each class costliest first

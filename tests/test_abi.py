@@ -63,6 +63,17 @@ def test_vertex_counts_reject_large_n_before_any_device_work():
     assert rc == -5 and "64 bits" in gl.graphlet_last_error()
 
 
+def test_noalloc_batched_refuses_oversized_batches_before_any_device_work():
+    # the pointers are never dereferenced: the graph count alone decides
+    if not os.path.exists(gl.LIB_PATH):
+        pytest.skip("library not built")
+    lib = gl.load()
+    assert lib.graphlet_count_batched_noalloc(None, None, None, 0) == -1
+    b = gl._Batch(gl.NOALLOC_MAX_GRAPHS + 1, 0x1000, 0x1000, 0)
+    assert lib.graphlet_count_batched_noalloc(ctypes.byref(b), 0x1000, None, 0) == -1
+    assert "allocation-free limit" in gl.graphlet_last_error()
+
+
 def test_binding_fails_loudly_when_library_is_missing(tmp_path, monkeypatch):
     monkeypatch.setattr(gl, "LIB_PATH", str(tmp_path / "missing.so"))
     monkeypatch.setattr(gl, "_lib", None)
