@@ -271,6 +271,88 @@ __device__ __forceinline__ int count_below(const int32_t *col2, int p, int e, in
   return hi - p;
 }
 
+// Counter bands of the heavy chunks.  c(x, y) <= min(nL, deg y), and degrees
+// do not decrease with rank, so the counters of a chunk of low-degree
+// endpoints need few bits: a chunk's counters are 2^lb-bit fields packed
+// 2^(5-lb) to a 32-bit word (lb = 1: 2 bits, ..., lb = 5: 32 bits), and a
+// chunk is as wide as kChunkWords words of its fields, so the y range of an
+// item is walked in fewer chunks where its endpoints have low degrees.  No
+// field can overflow into its neighbour.
+__device__ __forceinline__ void band_add(uint32_t *cnt, int lb, int d) {
+  const int fl = 5 - lb;
+  atomicAdd(&cnt[d >> fl], 1u << ((d & ((1 << fl) - 1)) << lb));
+}
+
+__device__ __forceinline__ uint32_t band_mask(int lb) {
+  return lb == 5 ? 0xffffffffu : (1u << (1 << lb)) - 1u;
+}
+
+__device__ __forceinline__ uint32_t band_get(const uint32_t *cnt, int lb, int d) {
+  const int fl = 5 - lb;
+  return (cnt[d >> fl] >> ((d & ((1 << fl) - 1)) << lb)) & band_mask(lb);
+}
+
+// Reads a counter and clears it (the first visitor gets the count, later
+// visitors 0).
+__device__ __forceinline__ uint32_t band_take(uint32_t *cnt, int lb, int d) {
+  const int fl = 5 - lb;
+  const int sh = (d & ((1 << fl) - 1)) << lb;
+  const uint32_t m = band_mask(lb);
+  return (atomicAnd(&cnt[d >> fl], ~(m << sh)) >> sh) & m;
+}
+
+// Sum of C(c, 2) over the counters of one word.
+__device__ __forceinline__ u64 band_word_pairs(uint32_t w, int lb) {
+  if (lb == 5) return choose2(w);
+  if (lb == 1) {  // c in 0..3: C(c, 2) = 0, 0, 1, 3
+    const uint32_t hi = (w >> 1) & 0x55555555u, lo = w & 0x55555555u;
+    return (u64)__popc(hi & ~lo) + 3ull * (u64)__popc(hi & lo);
+  }
+  const int b = 1 << lb;
+  const uint32_t m = band_mask(lb);
+  u64 s = 0;
+  for (int sh = 0; sh < 32; sh += b) s += choose2((w >> sh) & m);
+  return s;
+}
+
+// Ranks bounding the bands: R[j] (j = 0..3) is the first rank whose degree
+// exceeds the largest count of 2^(j+1)-bit fields (3, 15, 255, 65535); R[4]
+// is the first rank of degree at least 2 (endpoints of degree 1 close no
+// 4-cycle: c(x, y) <= 1).  Computed by threads 0..4, one binary search each.
+__device__ void band_ranks(const int32_t *deg2, int64_t n, int32_t *R) {
+  const int t = threadIdx.x;
+  if (t < 5) {
+    const int64_t lim = t == 4 ? 1 : (int64_t)band_mask(t + 1);
+    int64_t lo = 0, hi = n;  // first rank with deg2 > lim
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if ((int64_t)deg2[mid] > lim) hi = mid;
+      else lo = mid + 1;
+    }
+    R[t] = (int32_t)lo;
+  }
+}
+
+// The next chunk [c0, c1) of an item and its field width 2^lb: the widest
+// chunk whose counters fit (the same on every thread).
+__device__ __forceinline__ int band_chunk(int c0, int yb, int nL, const int32_t *R, int *lb_out) {
+  int64_t best = -1;
+  int blb = 5;
+  for (int lb = 1; lb <= 5; lb++) {
+    int64_t c1 = min((int64_t)yb, (int64_t)c0 + ((int64_t)kChunkWords << (5 - lb)));
+    if ((uint32_t)nL > band_mask(lb)) {
+      if (c0 >= R[lb - 1]) continue;
+      c1 = min(c1, (int64_t)R[lb - 1]);
+    }
+    if (c1 > best) {
+      best = c1;
+      blb = lb;
+    }
+  }
+  *lb_out = blb;
+  return (int)best;
+}
+
 // Heavy x, global mode, balanced.  Per item: the lower neighbours with at
 // least one wedge in the item's y range are compacted (cursor, end, next
 // entry).  Per chunk: the lists whose next entry falls in the chunk are
@@ -291,8 +373,10 @@ __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
   __shared__ int32_t vE[PER_EDGE ? kHeavyGroup : 1];
   __shared__ u64 red[32];
   __shared__ int s_item, s_nact, s_nsel;
+  __shared__ int32_t s_R[5];
   constexpr int RUN = 8;
   const int tid = threadIdx.x;
+  band_ranks(g.deg2, g.n, s_R);
   const int64_t nitems = *g.nitems;
   int32_t *cur = g.gcur + (size_t)blockIdx.x * g.lmax;
   int32_t *end = g.gbeg + (size_t)blockIdx.x * g.lmax;
@@ -313,10 +397,9 @@ __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
     const int item = s_item;
     if (item >= nitems) break;
     const int4 it = g.items[item];
-    const int x = it.x, ya = it.y, yb = it.z;
+    const int x = it.x, yb = it.z;
+    const int ya = max(it.y, s_R[4]);  // endpoints of degree <= 1 add nothing
     const int Lx = g.rp2[x], nL = g.lcnt[x];
-    const bool packed = nL < 65536;
-    const int K = packed ? 2 * kChunkWords : kChunkWords;
     // compact the lists with entries in [ya, yb)
     for (int b0 = 0; b0 < nL; b0 += kC4HeavyBlock) {
       const int i = b0 + tid;
@@ -352,8 +435,7 @@ __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
       // Each thread walks at most two active lists (nA <= nL < 2 x block),
       // cursors in registers, four entries per round; the chunk's counters
       // are summed and cleared by revisiting the walked runs (the first
-      // visitor of a counter takes its value).  Two barriers per chunk;
-      // counters are packed (nL < 2^16).
+      // visitor of a counter takes its value).  Two barriers per chunk.
       int pc[2], pe[2], nx[2];
 #pragma unroll
       for (int r = 0; r < 2; r++) {
@@ -367,8 +449,9 @@ __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
           nx[r] = nxt[i];
         }
       }
-      for (int c0 = ya; c0 < yb; c0 += K) {
-        const int c1 = min(c0 + K, yb);
+      for (int c0 = ya, c1; c0 < yb; c0 = c1) {
+        int lb;
+        c1 = band_chunk(c0, yb, nL, s_R, &lb);
         int b0[2];
 #pragma unroll
         for (int r = 0; r < 2; r++) {
@@ -389,8 +472,7 @@ __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
                 done = true;
                 nv = ys[q];
               } else {
-                const int d = ys[q] - c0;
-                atomicAdd(&cnt[d >> 1], (d & 1) ? 65536u : 1u);
+                band_add(cnt, lb, ys[q] - c0);
                 p++;
               }
             }
@@ -402,18 +484,15 @@ __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
         u64 part = 0;
 #pragma unroll
         for (int r = 0; r < 2; r++)
-          for (int p = b0[r]; p < pc[r]; p++) {
-            const int d = g.col2[p] - c0;
-            const int sh = (d & 1) * 16;
-            part += choose2((atomicAnd(&cnt[d >> 1], ~(0xffffu << sh)) >> sh) & 0xffffu);
-          }
+          for (int p = b0[r]; p < pc[r]; p++) part += choose2(band_take(cnt, lb, g.col2[p] - c0));
         acc += (u128)part;
         __syncthreads();
       }
       continue;
     }
-    for (int c0 = ya; c0 < yb; c0 += K) {
-      const int c1 = min(c0 + K, yb);
+    for (int c0 = ya, c1; c0 < yb; c0 = c1) {
+      int lb;
+      c1 = band_chunk(c0, yb, nL, s_R, &lb);
       if (tid == 0) s_nsel = 0;
       __syncthreads();
       for (int b0 = 0; b0 < nA; b0 += kC4HeavyBlock) {
@@ -458,9 +537,7 @@ __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
 #pragma unroll
           for (int r = 0; r < RUN; r++) {
             if (pos[r] < 0) continue;
-            const int d = yv[r] - c0;
-            if (packed) atomicAdd(&cnt[d >> 1], (d & 1) ? 65536u : 1u);
-            else atomicAdd(&cnt[d], 1u);
+            band_add(cnt, lb, yv[r] - c0);
           }
         }
         for (int j = tid; j < nG; j += kC4HeavyBlock) {
@@ -496,8 +573,7 @@ __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
             if (f < F) {
               j = upper_index_dev<int32_t>(vpre, nG, f);
               const int p = vcur[j] + (f - vpre[j]);
-              const int d = g.col2[p] - c0;
-              const uint32_t c = packed ? (cnt[d >> 1] >> ((d & 1) * 16)) & 0xffffu : cnt[d];
+              const uint32_t c = band_get(cnt, lb, g.col2[p] - c0);
               if (c >= 2) {
                 cr = c - 1;
                 atomicAdd(&g.C4w[p], cr);  // edge (v, y) at v's entry for y
@@ -524,23 +600,14 @@ __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
         // vcur / vpre still describe this chunk's wedges
         for (int f = tid; f < Fall; f += kC4HeavyBlock) {
           const int j = upper_index_dev<int32_t>(vpre, nS, f);
-          const int d = g.col2[vcur[j] + (f - vpre[j])] - c0;
-          uint32_t val;
-          if (packed) {
-            const int sh = (d & 1) * 16;
-            val = (atomicAnd(&cnt[d >> 1], ~(0xffffu << sh)) >> sh) & 0xffffu;
-          } else {
-            val = atomicExch(&cnt[d], 0u);
-          }
-          part += choose2(val);
+          part += choose2(band_take(cnt, lb, g.col2[vcur[j] + (f - vpre[j])] - c0));
         }
       } else {
         for (int w = tid; w < kChunkWords; w += kC4HeavyBlock) {
           const uint32_t val = cnt[w];
           if (val) {
             cnt[w] = 0;
-            if (packed) part += choose2(val & 0xffffu) + choose2(val >> 16);
-            else part += choose2(val);
+            part += band_word_pairs(val, lb);
           }
         }
       }

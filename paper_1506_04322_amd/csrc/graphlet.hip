@@ -499,6 +499,8 @@ int run(const gc_csr *G, gc_u128 out17[17], int64_t *per_edge_out, int64_t *loca
   c4.lcnt = pp.lcnt;
   c4.tpos = pp.tpos;
   c4.W = pp.W;
+  c4.deg2 = pp.deg2;
+  c4.n = n;
   c4.c4ni = &pp.acc->c4ni;
   c4.C4w = f.C4w;
   c4.list = pp.c4l;

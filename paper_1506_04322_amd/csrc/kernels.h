@@ -189,6 +189,8 @@ struct C4Args {
   int32_t *gvid;  // per slot (per-edge): list index of each active list
   int32_t *gcb;   // per slot (per-edge): run start of each list in the chunk
   int lmax;
+  const int32_t *deg2;  // degree of each rank (non-decreasing)
+  int64_t n;
 };
 
 // Dense hub slabs (global mode).  The costliest heavy vertices are counted
