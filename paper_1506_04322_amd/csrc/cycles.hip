@@ -353,6 +353,126 @@ __device__ __forceinline__ int band_chunk(int c0, int yb, int nL, const int32_t 
   return (int)best;
 }
 
+// One heavy item in global mode by walking: list i of the item (the part of
+// N(v_i) below x) is owned by thread i mod block, at most LPT per thread, with
+// its cursor and the next PF entries in registers (nL <= kWalkLists, so the
+// run queue of kHeavyGroup entries holds every list).  Per chunk, each thread
+// counts the buffered entries below the chunk's end and reloads its buffer
+// from the new cursor (the loads of the next chunk are in flight while the
+// chunk is summed); a run that continues past the buffer is queued (in LDS)
+// and read by a whole wave, two rows of 64 consecutive entries per round, so
+// long runs cost no serial walk.  The chunk's counters are summed and
+// cleared by a sweep of the LDS words.  Entries below the first counted rank
+// (endpoints of degree <= 1, which close no 4-cycle) are passed over in the
+// first chunk.  Two or three barriers per chunk, no global cursor state.
+template <int LPT>
+__device__ void heavy_walk_item(const C4Args &g, int Lx, int nL, int ya_item, int yb,
+                                uint32_t *cnt, const int32_t *R, int32_t *qpos, int32_t *qend,
+                                int *s_nq, u128 &acc) {
+  constexpr int PF = 8;
+  constexpr int NW = kC4HeavyBlock / kWave;
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+  const int ys = max(ya_item, R[4]);
+  if (tid == 0) s_nq[0] = s_nq[1] = 0;
+  int p[LPT], e[LPT], buf[LPT][PF];
+#pragma unroll
+  for (int r = 0; r < LPT; r++) {
+    const int i = tid + r * kC4HeavyBlock;
+    p[r] = 0;
+    e[r] = 0;
+    if (i < nL) {
+      const int q = Lx + i;
+      const int s = g.rp2[g.col2[q]];
+      e[r] = g.tpos[q];
+      p[r] = ya_item > 0 ? s + lower_bound_dev<int32_t>(g.col2 + s, e[r] - s, ys) : s;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < LPT; r++)
+#pragma unroll
+    for (int k = 0; k < PF; k++) buf[r][k] = p[r] + k < e[r] ? g.col2[p[r] + k] : INT32_MAX;
+  __syncthreads();
+  int par = 0;
+  for (int c0 = ys, c1; c0 < yb; c0 = c1, par ^= 1) {
+    int lb;
+    c1 = band_chunk(c0, yb, nL, R, &lb);
+    int qs[LPT];  // queue slot of a list whose run goes on past its buffer, or -1
+#pragma unroll
+    for (int r = 0; r < LPT; r++) {
+      int taken = 0;
+      bool live = true;
+#pragma unroll
+      for (int k = 0; k < PF; k++) {
+        live = live && buf[r][k] < c1;
+        if (live) {
+          if (buf[r][k] >= c0) band_add(cnt, lb, buf[r][k] - c0);
+          taken++;
+        }
+      }
+      qs[r] = -1;
+      if (taken == PF && p[r] + PF < e[r]) {
+        // each list is queued at most once per chunk: the queue holds them all
+        const int slot = atomicAdd(&s_nq[par], 1);
+        qpos[slot] = p[r] + PF;
+        qend[slot] = e[r];
+        qs[r] = slot;
+      }
+      if (qs[r] < 0 && taken > 0) {
+        p[r] += taken;
+#pragma unroll
+        for (int k = 0; k < PF; k++) buf[r][k] = p[r] + k < e[r] ? g.col2[p[r] + k] : INT32_MAX;
+      }
+    }
+    __syncthreads();
+    const int nq = s_nq[par];
+    if (tid == 0) s_nq[par ^ 1] = 0;  // the next chunk's queue
+    if (nq > 0) {  // the same on every thread
+      for (int qi = wave; qi < nq; qi += NW) {
+        int pos = qpos[qi];
+        const int qe = qend[qi];
+        while (true) {  // every exit is decided by a ballot: the same on the wave
+          const int p0 = pos + lane, p1 = pos + kWave + lane;
+          const int y0 = p0 < qe ? g.col2[p0] : INT32_MAX;
+          const int y1 = p1 < qe ? g.col2[p1] : INT32_MAX;
+          const bool in0 = y0 < c1, in1 = y1 < c1;
+          if (in0 && y0 >= c0) band_add(cnt, lb, y0 - c0);
+          if (in1 && y1 >= c0) band_add(cnt, lb, y1 - c0);
+          const u64 b0 = __ballot(!in0), b1 = __ballot(!in1);
+          if (b0) {
+            pos += __ffsll((long long)b0) - 1;
+            break;
+          }
+          if (b1) {
+            pos += kWave + __ffsll((long long)b1) - 1;
+            break;
+          }
+          pos += 2 * kWave;
+        }
+        if (lane == 0) qpos[qi] = pos;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < LPT; r++)
+        if (qs[r] >= 0) {
+          p[r] = qpos[qs[r]];
+#pragma unroll
+          for (int k = 0; k < PF; k++) buf[r][k] = p[r] + k < e[r] ? g.col2[p[r] + k] : INT32_MAX;
+        }
+    }
+    u64 part = 0;
+    for (int w = tid; w < kChunkWords; w += kC4HeavyBlock) {
+      const uint32_t v = cnt[w];
+      if (v) {
+        cnt[w] = 0;
+        part += band_word_pairs(v, lb);
+      }
+    }
+    acc += (u128)part;
+    __syncthreads();
+  }
+  __syncthreads();  // s_item is rewritten next
+}
+
 // Heavy x, global mode, balanced.  Per item: the lower neighbours with at
 // least one wedge in the item's y range are compacted (cursor, end, next
 // entry).  Per chunk: the lists whose next entry falls in the chunk are
@@ -372,7 +492,7 @@ __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
   __shared__ int32_t vpre[kHeavyGroup + 1], vcur[kHeavyGroup], sums[kC4HeavyBlock / kWave + 1];
   __shared__ int32_t vE[PER_EDGE ? kHeavyGroup : 1];
   __shared__ u64 red[32];
-  __shared__ int s_item, s_nact, s_nsel;
+  __shared__ int s_item, s_nact, s_nsel, s_nq[2];
   __shared__ int32_t s_R[5];
   constexpr int RUN = 8;
   const int tid = threadIdx.x;
@@ -400,6 +520,13 @@ __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
     const int x = it.x, yb = it.z;
     const int ya = max(it.y, s_R[4]);  // endpoints of degree <= 1 add nothing
     const int Lx = g.rp2[x], nL = g.lcnt[x];
+    if (!PER_EDGE && nL <= kWalkLists) {  // the same on every thread
+      if (nL <= kC4HeavyBlock)
+        heavy_walk_item<1>(g, Lx, nL, it.y, yb, cnt, s_R, vpre, vcur, s_nq, acc);
+      else
+        heavy_walk_item<2>(g, Lx, nL, it.y, yb, cnt, s_R, vpre, vcur, s_nq, acc);
+      continue;
+    }
     // compact the lists with entries in [ya, yb)
     for (int b0 = 0; b0 < nL; b0 += kC4HeavyBlock) {
       const int i = b0 + tid;
@@ -429,67 +556,6 @@ __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
     }
     __syncthreads();
     const int nA = s_nact;
-    if (!PER_EDGE && nL <= kWalkLists) {
-      // Few lower neighbours, hence few wedges per chunk: the selection,
-      // scan and cursor round trips of the general path would dominate.
-      // Each thread walks at most two active lists (nA <= nL < 2 x block),
-      // cursors in registers, four entries per round; the chunk's counters
-      // are summed and cleared by revisiting the walked runs (the first
-      // visitor of a counter takes its value).  Two barriers per chunk.
-      int pc[2], pe[2], nx[2];
-#pragma unroll
-      for (int r = 0; r < 2; r++) {
-        const int i = tid + r * kC4HeavyBlock;
-        pc[r] = 0;
-        pe[r] = 0;
-        nx[r] = INT32_MAX;
-        if (i < nA) {
-          pc[r] = cur[i];
-          pe[r] = end[i];
-          nx[r] = nxt[i];
-        }
-      }
-      for (int c0 = ya, c1; c0 < yb; c0 = c1) {
-        int lb;
-        c1 = band_chunk(c0, yb, nL, s_R, &lb);
-        int b0[2];
-#pragma unroll
-        for (int r = 0; r < 2; r++) {
-          b0[r] = pc[r];
-          if (nx[r] >= c1) continue;
-          // entries before pc are below c0; col2[pc] = nx is in the chunk
-          int p = pc[r], nv = INT32_MAX;
-          const int e = pe[r];
-          bool done = false;
-          while (!done) {
-            int ys[4];
-#pragma unroll
-            for (int q = 0; q < 4; q++) ys[q] = p + q < e ? g.col2[p + q] : INT32_MAX;
-#pragma unroll
-            for (int q = 0; q < 4; q++) {
-              if (done) continue;
-              if (ys[q] >= c1) {
-                done = true;
-                nv = ys[q];
-              } else {
-                band_add(cnt, lb, ys[q] - c0);
-                p++;
-              }
-            }
-          }
-          pc[r] = p;
-          nx[r] = nv;
-        }
-        __syncthreads();
-        u64 part = 0;
-#pragma unroll
-        for (int r = 0; r < 2; r++)
-          for (int p = b0[r]; p < pc[r]; p++) part += choose2(band_take(cnt, lb, g.col2[p] - c0));
-        acc += (u128)part;
-        __syncthreads();
-      }
-      continue;
-    }
     for (int c0 = ya, c1; c0 < yb; c0 = c1) {
       int lb;
       c1 = band_chunk(c0, yb, nL, s_R, &lb);

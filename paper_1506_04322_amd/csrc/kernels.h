@@ -53,11 +53,12 @@ constexpr int kSparseChunk = 8192;
 constexpr int kChunkWords = 32768;
 constexpr int kC4HeavyBlock = 1024;
 constexpr int kHeavyGroup = 2048;
-// Heavy items of vertices with at most this many lower neighbours take the
-// walking path (one thread per list, cursors in registers); it must stay
-// below twice the heavy workgroup size.
-constexpr int kWalkLists = 1200;
-static_assert(kWalkLists < 2 * kC4HeavyBlock, "two lists per thread");
+// Heavy items (global mode) of vertices with at most this many lower
+// neighbours take the walking path (each thread owns up to two lists,
+// cursors in registers); long runs are queued for whole waves, and the
+// queue (kHeavyGroup entries) holds every list.
+constexpr int kWalkLists = 2 * kC4HeavyBlock;
+static_assert(kWalkLists <= kHeavyGroup, "the run queue holds every list");
 // Target wedges per heavy work item.
 constexpr u64 kPieceWork = u64(1) << 21;
 // Concurrent workgroups of the global-memory clique kernel.

@@ -311,6 +311,29 @@ def test_dense_hub_slabs_rmat17():
 kDenseSlab = 256
 
 
+@pytest.mark.parametrize("nv", [700, 2000, 3000])
+def test_heavy_items_long_runs(nv):
+    # x is adjacent to nv vertices v, each adjacent to the same 30 vertices y
+    # below x in the degree order (ties by id): every list of x's heavy item
+    # has a run of 30 in one chunk, longer than a thread's buffer, so all nv
+    # lists go to the long-run queue together (one or two lists per thread up
+    # to 2048 lists; the general path above); the y's are heavy too, with
+    # runs of every length up to 29
+    ny = 30
+    x = ny + nv
+    edges = [(y, ny + i) for i in range(nv) for y in range(ny)] + [(ny + i, x) for i in range(nv)]
+    g = graphgen.from_edges(x + 1, edges)
+    want = oracle.identity_route(g)
+    gl.graphlet_timing_enable(True)
+    try:
+        got = gl.graphlet_count(dev(g.row_ptr), dev(g.col), g.n, dense="off", validate=True)
+        t = gl.graphlet_last_timing()
+    finally:
+        gl.graphlet_timing_enable(False)
+    assert got == want
+    assert t["heavy_items"] >= 2 and t["wedges_heavy"] >= nv * ny
+
+
 # ------------------------------------------------------------ per-edge local vectors
 
 
