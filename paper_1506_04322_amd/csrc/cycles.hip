@@ -292,27 +292,58 @@ __device__ __forceinline__ uint32_t band_get(const uint32_t *cnt, int lb, int d)
   return (cnt[d >> fl] >> ((d & ((1 << fl) - 1)) << lb)) & band_mask(lb);
 }
 
-// Reads a counter and clears it (the first visitor gets the count, later
-// visitors 0).
-__device__ __forceinline__ uint32_t band_take(uint32_t *cnt, int lb, int d) {
-  const int fl = 5 - lb;
-  const int sh = (d & ((1 << fl) - 1)) << lb;
-  const uint32_t m = band_mask(lb);
-  return (atomicAnd(&cnt[d >> fl], ~(m << sh)) >> sh) & m;
+// Sum of C(c, 2) over the counters of four consecutive words (one 16-byte
+// LDS read of the sweep).  Byte counters: sum c^2 - sum c from byte dot
+// products (4-bit counters split into two byte sets); 2-bit: popcounts.
+__device__ __forceinline__ u64 band_quad_pairs(uint4 v, int lb) {
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+  if (lb == 1) {  // c in 0..3: C(c, 2) = 0, 0, 1, 3
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      const uint32_t hi = (w[i] >> 1) & 0x55555555u, lo = w[i] & 0x55555555u;
+      s += (uint32_t)__popc(hi & ~lo) + 3u * (uint32_t)__popc(hi & lo);
+    }
+    return s;
+  }
+  if (lb <= 3) {  // at most 32 counters of 15, or 16 of 255: the sums fit 32 bits
+    uint32_t sq = 0, sm = 0;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      if (lb == 2) {
+        const uint32_t lo = w[i] & 0x0f0f0f0fu, hi = (w[i] >> 4) & 0x0f0f0f0fu;
+        sq = __builtin_amdgcn_udot4(lo, lo, sq, false);
+        sq = __builtin_amdgcn_udot4(hi, hi, sq, false);
+        sm = __builtin_amdgcn_udot4(lo, 0x01010101u, sm, false);
+        sm = __builtin_amdgcn_udot4(hi, 0x01010101u, sm, false);
+      } else {
+        sq = __builtin_amdgcn_udot4(w[i], w[i], sq, false);
+        sm = __builtin_amdgcn_udot4(w[i], 0x01010101u, sm, false);
+      }
+    }
+    return (sq - sm) / 2;
+  }
+  u64 s = 0;
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    if (lb == 4) s += choose2(w[i] & 0xffffu) + choose2(w[i] >> 16);
+    else s += choose2(w[i]);
+  }
+  return s;
 }
 
-// Sum of C(c, 2) over the counters of one word.
-__device__ __forceinline__ u64 band_word_pairs(uint32_t w, int lb) {
-  if (lb == 5) return choose2(w);
-  if (lb == 1) {  // c in 0..3: C(c, 2) = 0, 0, 1, 3
-    const uint32_t hi = (w >> 1) & 0x55555555u, lo = w & 0x55555555u;
-    return (u64)__popc(hi & ~lo) + 3ull * (u64)__popc(hi & lo);
+// This thread's share of the chunk's sum of C(c, 2), its counters cleared.
+__device__ __forceinline__ u64 band_sweep(uint32_t *cnt, int lb) {
+  u64 part = 0;
+  uint4 *c4 = reinterpret_cast<uint4 *>(cnt);
+  for (int w = threadIdx.x; w < kChunkWords / 4; w += blockDim.x) {
+    const uint4 v = c4[w];
+    if (v.x | v.y | v.z | v.w) {
+      c4[w] = make_uint4(0u, 0u, 0u, 0u);
+      part += band_quad_pairs(v, lb);
+    }
   }
-  const int b = 1 << lb;
-  const uint32_t m = band_mask(lb);
-  u64 s = 0;
-  for (int sh = 0; sh < 32; sh += b) s += choose2((w >> sh) & m);
-  return s;
+  return part;
 }
 
 // Ranks bounding the bands: R[j] (j = 0..3) is the first rank whose degree
@@ -359,17 +390,19 @@ __device__ __forceinline__ int band_chunk(int c0, int yb, int nL, const int32_t 
 // run queue of kHeavyGroup entries holds every list).  Per chunk, each thread
 // counts the buffered entries below the chunk's end and reloads its buffer
 // from the new cursor (the loads of the next chunk are in flight while the
-// chunk is summed); a run that continues past the buffer is queued (in LDS)
-// and read by a whole wave, two rows of 64 consecutive entries per round, so
-// long runs cost no serial walk.  The chunk's counters are summed and
-// cleared by a sweep of the LDS words.  Entries below the first counted rank
-// (endpoints of degree <= 1, which close no 4-cycle) are passed over in the
-// first chunk.  Two or three barriers per chunk, no global cursor state.
+// chunk is summed); a run that continues past the buffer takes up to three
+// more rounds of 8 entries (all of the thread's lists at once), and one
+// longer still is queued (in LDS) and read by a whole wave, two runs at a
+// time, two rows of 64 consecutive entries of each per round.  The chunk's
+// counters are summed and cleared by a sweep of the LDS words, 16 bytes per
+// read.  Entries below the first counted rank (endpoints of degree <= 1,
+// which close no 4-cycle) are passed over in the first chunk.  Two or three
+// barriers per chunk, no global cursor state.
 template <int LPT>
 __device__ void heavy_walk_item(const C4Args &g, int Lx, int nL, int ya_item, int yb,
                                 uint32_t *cnt, const int32_t *R, int32_t *qpos, int32_t *qend,
                                 int *s_nq, u128 &acc) {
-  constexpr int PF = 8;
+  constexpr int PF = 8, XR = 8;
   constexpr int NW = kC4HeavyBlock / kWave;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   const int ys = max(ya_item, R[4]);
@@ -396,7 +429,9 @@ __device__ void heavy_walk_item(const C4Args &g, int Lx, int nL, int ya_item, in
   for (int c0 = ys, c1; c0 < yb; c0 = c1, par ^= 1) {
     int lb;
     c1 = band_chunk(c0, yb, nL, R, &lb);
-    int qs[LPT];  // queue slot of a list whose run goes on past its buffer, or -1
+    int qs[LPT];  // queue slot of a list whose run goes on past what it read, or -1
+    int q[LPT];   // cursor after the entries read so far in this chunk
+    bool run[LPT];
 #pragma unroll
     for (int r = 0; r < LPT; r++) {
       int taken = 0;
@@ -409,16 +444,50 @@ __device__ void heavy_walk_item(const C4Args &g, int Lx, int nL, int ya_item, in
           taken++;
         }
       }
+      q[r] = p[r] + taken;
+      run[r] = taken == PF && q[r] < e[r];
+    }
+    // runs longer than the buffer: up to three more rounds of XR entries
+    // here, the loads of all the thread's lists in flight together
+#pragma unroll
+    for (int round = 0; round < 3; round++) {
+      bool any = false;
+#pragma unroll
+      for (int r = 0; r < LPT; r++) any = any || run[r];
+      if (!any) break;
+      int yv[LPT][XR];
+#pragma unroll
+      for (int r = 0; r < LPT; r++)
+#pragma unroll
+        for (int k = 0; k < XR; k++)
+          yv[r][k] = run[r] && q[r] + k < e[r] ? g.col2[q[r] + k] : INT32_MAX;
+#pragma unroll
+      for (int r = 0; r < LPT; r++) {
+        int t = 0;
+        bool lv = run[r];
+#pragma unroll
+        for (int k = 0; k < XR; k++) {
+          lv = lv && yv[r][k] < c1;
+          if (lv) {
+            if (yv[r][k] >= c0) band_add(cnt, lb, yv[r][k] - c0);
+            t++;
+          }
+        }
+        q[r] += t;
+        run[r] = run[r] && t == XR && q[r] < e[r];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < LPT; r++) {
       qs[r] = -1;
-      if (taken == PF && p[r] + PF < e[r]) {
+      if (run[r]) {
         // each list is queued at most once per chunk: the queue holds them all
         const int slot = atomicAdd(&s_nq[par], 1);
-        qpos[slot] = p[r] + PF;
+        qpos[slot] = q[r];
         qend[slot] = e[r];
         qs[r] = slot;
-      }
-      if (qs[r] < 0 && taken > 0) {
-        p[r] += taken;
+      } else if (q[r] != p[r]) {
+        p[r] = q[r];
 #pragma unroll
         for (int k = 0; k < PF; k++) buf[r][k] = p[r] + k < e[r] ? g.col2[p[r] + k] : INT32_MAX;
       }
@@ -427,28 +496,48 @@ __device__ void heavy_walk_item(const C4Args &g, int Lx, int nL, int ya_item, in
     const int nq = s_nq[par];
     if (tid == 0) s_nq[par ^ 1] = 0;  // the next chunk's queue
     if (nq > 0) {  // the same on every thread
-      for (int qi = wave; qi < nq; qi += NW) {
-        int pos = qpos[qi];
-        const int qe = qend[qi];
-        while (true) {  // every exit is decided by a ballot: the same on the wave
-          const int p0 = pos + lane, p1 = pos + kWave + lane;
-          const int y0 = p0 < qe ? g.col2[p0] : INT32_MAX;
-          const int y1 = p1 < qe ? g.col2[p1] : INT32_MAX;
-          const bool in0 = y0 < c1, in1 = y1 < c1;
-          if (in0 && y0 >= c0) band_add(cnt, lb, y0 - c0);
-          if (in1 && y1 >= c0) band_add(cnt, lb, y1 - c0);
-          const u64 b0 = __ballot(!in0), b1 = __ballot(!in1);
-          if (b0) {
-            pos += __ffsll((long long)b0) - 1;
-            break;
-          }
-          if (b1) {
-            pos += kWave + __ffsll((long long)b1) - 1;
-            break;
-          }
-          pos += 2 * kWave;
+      // a wave reads QR runs at once, two rows of 64 entries of each per round
+      constexpr int QR = 2;
+      for (int q0 = wave * QR; q0 < nq; q0 += NW * QR) {
+        int pos[QR], qe[QR];
+        bool go[QR];  // the same on the wave: from LDS, then from ballots
+#pragma unroll
+        for (int r = 0; r < QR; r++) {
+          go[r] = q0 + r < nq;
+          pos[r] = go[r] ? qpos[q0 + r] : 0;
+          qe[r] = go[r] ? qend[q0 + r] : 0;
         }
-        if (lane == 0) qpos[qi] = pos;
+        while (go[0] || go[1]) {
+          int y0[QR], y1[QR];
+#pragma unroll
+          for (int r = 0; r < QR; r++) {
+            const int p0 = pos[r] + lane, p1 = pos[r] + kWave + lane;
+            y0[r] = go[r] && p0 < qe[r] ? g.col2[p0] : INT32_MAX;
+            y1[r] = go[r] && p1 < qe[r] ? g.col2[p1] : INT32_MAX;
+          }
+#pragma unroll
+          for (int r = 0; r < QR; r++) {
+            if (!go[r]) continue;
+            const bool in0 = y0[r] < c1, in1 = y1[r] < c1;
+            if (in0 && y0[r] >= c0) band_add(cnt, lb, y0[r] - c0);
+            if (in1 && y1[r] >= c0) band_add(cnt, lb, y1[r] - c0);
+            const u64 b0 = __ballot(!in0), b1 = __ballot(!in1);
+            if (b0) {
+              pos[r] += __ffsll((long long)b0) - 1;
+              go[r] = false;
+            } else if (b1) {
+              pos[r] += kWave + __ffsll((long long)b1) - 1;
+              go[r] = false;
+            } else {
+              pos[r] += 2 * kWave;
+            }
+          }
+        }
+        if (lane == 0) {
+#pragma unroll
+          for (int r = 0; r < QR; r++)
+            if (q0 + r < nq) qpos[q0 + r] = pos[r];
+        }
       }
       __syncthreads();
 #pragma unroll
@@ -459,36 +548,29 @@ __device__ void heavy_walk_item(const C4Args &g, int Lx, int nL, int ya_item, in
           for (int k = 0; k < PF; k++) buf[r][k] = p[r] + k < e[r] ? g.col2[p[r] + k] : INT32_MAX;
         }
     }
-    u64 part = 0;
-    for (int w = tid; w < kChunkWords; w += kC4HeavyBlock) {
-      const uint32_t v = cnt[w];
-      if (v) {
-        cnt[w] = 0;
-        part += band_word_pairs(v, lb);
-      }
-    }
-    acc += (u128)part;
+    acc += (u128)band_sweep(cnt, lb);
     __syncthreads();
   }
   __syncthreads();  // s_item is rewritten next
 }
 
-// Heavy x, global mode, balanced.  Per item: the lower neighbours with at
+// Heavy x, balanced (global mode: vertices with more than kWalkLists lower
+// neighbours; per-edge mode: every heavy vertex).  Per item: the lower neighbours with at
 // least one wedge in the item's y range are compacted (cursor, end, next
 // entry).  Per chunk: the lists whose next entry falls in the chunk are
 // selected by a coalesced pass over the next entries; in groups, the run of
 // each selected list inside the chunk is measured, then the runs are read
 // flat, so threads share long and short lists evenly and neighbouring
-// threads read neighbouring entries.  Counters are zero between chunks: a
-// chunk with few wedges is summed and cleared by revisiting its wedges (the
-// first visitor of a counter takes its value), a dense one by a sweep.
+// threads read neighbouring entries (in the last chunk below x a run is the
+// rest of its list, with no search).  Counters are zero between chunks: a
+// sweep sums and clears them.
 // Per-edge mode revisits each chunk's wedges once its counts are complete
 // (before they are cleared): wedge x - v - y adds c(x, y) - 1 to edge (v, y)
 // and to edge (x, v), each at a directed entry (folded into the edge's upper
 // position afterwards).
 template <bool PER_EDGE>
 __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
-  __shared__ uint32_t cnt[kChunkWords];
+  __shared__ __align__(16) uint32_t cnt[kChunkWords];
   __shared__ int32_t vpre[kHeavyGroup + 1], vcur[kHeavyGroup], sums[kC4HeavyBlock / kWave + 1];
   __shared__ int32_t vE[PER_EDGE ? kHeavyGroup : 1];
   __shared__ u64 red[32];
@@ -573,19 +655,18 @@ __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
       __syncthreads();
       const int nS = s_nsel;
       if (nS == 0) continue;  // uniform: no wedge of this item in the chunk
-      int Fall = 0;
       for (int g0 = 0; g0 < nS; g0 += kHeavyGroup) {
         const int nG = min(kHeavyGroup, nS - g0);
         for (int j = tid; j < nG; j += kC4HeavyBlock) {
           const int i = sel[g0 + j];
           const int p = cur[i];
           vcur[j] = p;
-          vpre[j] = count_below(g.col2, p, end[i], c1);
+          // the last chunk below x: every entry left in the list is in it
+          vpre[j] = c1 >= x ? end[i] - p : count_below(g.col2, p, end[i], c1);
         }
         __syncthreads();
         scan_excl<kC4HeavyBlock>(vpre, nG, sums);
         const int F = vpre[nG];
-        Fall += F;
         for (int f0 = tid * RUN; f0 < F; f0 += kC4HeavyBlock * RUN) {
           int j = upper_index_dev<int32_t>(vpre, nG, f0);
           int pos[RUN], yv[RUN];
@@ -661,23 +742,7 @@ __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
           __syncthreads();
         }
       }
-      u64 part = 0;
-      if (nS <= kHeavyGroup && Fall <= kSparseChunk) {
-        // vcur / vpre still describe this chunk's wedges
-        for (int f = tid; f < Fall; f += kC4HeavyBlock) {
-          const int j = upper_index_dev<int32_t>(vpre, nS, f);
-          part += choose2(band_take(cnt, lb, g.col2[vcur[j] + (f - vpre[j])] - c0));
-        }
-      } else {
-        for (int w = tid; w < kChunkWords; w += kC4HeavyBlock) {
-          const uint32_t val = cnt[w];
-          if (val) {
-            cnt[w] = 0;
-            part += band_word_pairs(val, lb);
-          }
-        }
-      }
-      acc += (u128)part;
+      acc += (u128)band_sweep(cnt, lb);
       __syncthreads();
     }
   }

@@ -45,9 +45,6 @@ constexpr int kHashSlots = 2048;
 constexpr u64 kMediumWedges = 16384;
 constexpr int kMediumSlots = 22528;
 constexpr int kMediumBlock = 1024;
-// A chunk with at most this many wedges is summed and cleared by revisiting
-// its wedges instead of sweeping every counter word.
-constexpr int kSparseChunk = 8192;
 // Heavy wedge vertices: LDS counter chunk of 128 KiB; lower neighbours are
 // measured in groups of kHeavyGroup per chunk.
 constexpr int kChunkWords = 32768;
