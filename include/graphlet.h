@@ -61,6 +61,8 @@ extern "C" {
  * a slab pass is cheaper than their wedges by work items. */
 #define GC_DENSE_ALL 2u /* up to 8192 costliest heavy vertices in dense slabs */
 #define GC_DENSE_OFF 4u /* no dense slabs */
+/* Serving only (gc_server_create): no batch lane, every request on a slot. */
+#define GC_SERVE_NO_LANE 256u
 
 /*
  * An undirected simple graph in CSR form, in DEVICE memory owned by the
@@ -247,7 +249,8 @@ int graphlet_count_batched_noalloc(const gc_batch *b, int64_t *out, void *stream
  * rows written).  Stream-ordered; returns when out is complete.  The size
  * classes run on streams of the library's own (created on first use,
  * one set per device, kept until the process ends), joined to `stream`;
- * calls from several host threads run one after another.
+ * calls from several host threads queue their launches on them in turn
+ * (a lock covers the launches, not the wait for the results).
  */
 int graphlet_batch_vertex(const gc_batch *b, uint64_t *out, void *stream, uint32_t flags);
 
@@ -361,7 +364,15 @@ int graphlet_last_timing(gc_timing *out);
  * stream, and its CSR freed when its counts are on the host.  Requests that
  * arrive while others run are admitted as slots and memory free up, so the
  * work of several requests overlaps on the device; a request's result is the
- * same as a standalone graphlet_count of its graph.
+ * same as a standalone graphlet_count of its graph.  Small graphs (at most
+ * GC_BATCH_MAX_N vertices) go to the batch lane instead: every pending small
+ * request, up to the lane's capacity (1024 graphs, 2^18 vertices, 2^22
+ * adjacency entries), is counted in one graphlet_count_batched call on the
+ * lane's own stream, while requests arriving meanwhile wait for the next
+ * batch; the lane's buffers (about 17 MB of device memory, and pinned host
+ * memory) are charged to the budget for the server's life, and the lane is
+ * left out when they would take more than a quarter of the budget, or with
+ * the flag GC_SERVE_NO_LANE.
  *   gc_server_create   budget in bytes of device memory, slots = concurrent
  *                      requests (1..64, one stream each), flags as for
  *                      graphlet_count (GC_VALIDATE checks every request).
@@ -416,6 +427,8 @@ typedef struct gc_serve_stats {
   int64_t submitted, completed, failed, rejected, cancelled, pending, running;
   size_t bytes_in_use, bytes_peak, budget;
   double p50_ms, p99_ms, mean_ms, elapsed_s, graphs_per_s, edges_per_s;
+  int64_t batches;  /* batched calls of the batch lane */
+  int64_t batched;  /* requests counted by them */
 } gc_serve_stats;
 
 gc_server *gc_server_create(size_t hbm_budget, int slots, uint32_t flags);

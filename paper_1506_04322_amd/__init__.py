@@ -26,6 +26,7 @@ NAMES = ["g2_1", "g2_2", "g3_1", "g3_2", "g3_3", "g3_4"] + [f"g4_{i}" for i in r
 GC_VALIDATE = 1
 GC_DENSE_ALL = 2
 GC_DENSE_OFF = 4
+GC_SERVE_NO_LANE = 256
 ERRORS = {
     -1: "GC_EINVAL", -2: "GC_ENOTSORTED", -3: "GC_ESELFLOOP", -4: "GC_EASYMMETRIC",
     -5: "GC_EOVERFLOW", -6: "GC_ENOMEM", -7: "GC_EHIP", -8: "GC_EINTERNAL",
@@ -99,7 +100,8 @@ class _ServeStats(ctypes.Structure):
                  "running")] + \
                [(name, ctypes.c_size_t) for name in ("bytes_in_use", "bytes_peak", "budget")] + \
                [(name, ctypes.c_double) for name in
-                ("p50_ms", "p99_ms", "mean_ms", "elapsed_s", "graphs_per_s", "edges_per_s")]
+                ("p50_ms", "p99_ms", "mean_ms", "elapsed_s", "graphs_per_s", "edges_per_s")] + \
+               [(name, ctypes.c_int64) for name in ("batches", "batched")]
 
 class _PlanInfo(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int), ("classes", ctypes.c_int),
@@ -536,10 +538,11 @@ class Server:
     poll() return the 17 counts (python ints) and the latency in ms.
     """
 
-    def __init__(self, budget_bytes: int, slots: int = 4, validate: bool = False):
+    def __init__(self, budget_bytes: int, slots: int = 4, validate: bool = False,
+                 batch_lane: bool = True):
         self._lib = load()
-        h = self._lib.gc_server_create(int(budget_bytes), int(slots),
-                                       GC_VALIDATE if validate else 0)
+        flags = (GC_VALIDATE if validate else 0) | (0 if batch_lane else GC_SERVE_NO_LANE)
+        h = self._lib.gc_server_create(int(budget_bytes), int(slots), flags)
         if not h:
             raise GraphletError(-1, self._lib.gc_server_last_error().decode())
         self._h = h

@@ -351,13 +351,16 @@ extern "C" int graphlet_batch_vertex(const gc_batch *b, uint64_t *out, void *str
     if (e == hipSuccess)
       (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     // the classes run on streams of their own, after the uploads on s, and s
-    // waits for all of them (largest class first, so its tail overlaps the rest)
-    std::lock_guard<std::mutex> lk(gc::g_bv_mu);
+    // waits for all of them (largest class first, so its tail overlaps the
+    // rest).  The lock covers the stream pool and each call's attribute,
+    // launch and event sequence, not the wait for the results: calls from
+    // several threads queue their launches in turn and overlap on the device.
     hipStream_t *cs = nullptr;
-    if (e == hipSuccess) e = gc::class_streams(dev, &cs);
     hipEvent_t fork = nullptr;
     std::vector<hipEvent_t> done;
     std::vector<int> launched;
+    std::unique_lock<std::mutex> lk(gc::g_bv_mu);
+    if (e == hipSuccess) e = gc::class_streams(dev, &cs);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventRecord(fork, s);
     for (int c = gc::kBvClasses - 1; c >= 0 && e == hipSuccess; c--) {
@@ -392,6 +395,7 @@ extern "C" int graphlet_batch_vertex(const gc_batch *b, uint64_t *out, void *str
       }
       if (e == hipSuccess) e = hipStreamWaitEvent(s, ev, 0);
     }
+    lk.unlock();
     // on an error part way, the classes already launched finish before the
     // order and counters are freed
     if (e != hipSuccess)

@@ -12,6 +12,17 @@
 // counts are on the host; each request runs the same graphlet_count path as
 // a standalone call, so its result does not depend on what else is running.
 //
+// Small graphs (at most GC_BATCH_MAX_N vertices) take the batch lane: one
+// thread with its own stream and preallocated device and pinned host buffers
+// (charged to the budget once, at creation) gathers every pending small
+// request, up to the lane's capacity, into one concatenated CSR, uploads it in
+// one copy and counts the whole batch with one launch per size class of the
+// batched kernel (one workgroup per graph); requests arriving meanwhile form
+// the next batch.  A batch that fails (a graph breaking the CSR contract
+// under validation) is counted again one request at a time, so the failure
+// stays with its own request.  Batched counts are the same integers as the
+// single-graph path's.
+//
 // Resident graphs: a registered graph keeps its CSR (two buffers, the live
 // one and a spare) and its counts on the device until it is unregistered.
 // Edge updates against it are requests too; those of one graph run one at a
@@ -80,6 +91,25 @@ struct Request {
 
 }  // namespace
 
+namespace {
+
+// Capacity of one batch of the batch lane.
+constexpr int kLaneGraphs = 1024;
+constexpr int64_t kLaneRows = int64_t(1) << 18;     // vertices
+constexpr int64_t kLaneEntries = int64_t(1) << 22;  // adjacency entries
+
+struct Lane {
+  bool on = false;
+  size_t bytes = 0;  // device memory, charged to the budget while the server lives
+  hipStream_t st = nullptr;
+  int64_t *d_off = nullptr, *h_off = nullptr;
+  int32_t *d_rp = nullptr, *h_rp = nullptr;
+  int32_t *d_col = nullptr, *h_col = nullptr;
+  int64_t *d_out = nullptr, *h_out = nullptr;
+};
+
+}  // namespace
+
 struct gc_server {
   size_t budget = 0;
   size_t in_use = 0;
@@ -93,6 +123,10 @@ struct gc_server {
   std::unordered_map<int64_t, Request *> all;
   std::unordered_map<int64_t, Resident *> graphs;
   std::vector<std::thread> workers;
+  Lane lane;
+  std::thread lane_thread;
+  std::condition_variable cv_lane;
+  int64_t batches = 0, batched = 0;
   int64_t next_id = 1;
   bool stop = false;
   int running = 0;
@@ -174,7 +208,8 @@ void run_register(gc_server *S, Request *r, hipStream_t st) {
     err = hipGetErrorString(e);
   } else {
     gc_csr g{G->n, G->nnz, G->rp[0], G->col[0]};
-    rc = graphlet_count(&g, r->out, nullptr, nullptr, 0, st, S->flags | GC_VALIDATE);
+    rc = graphlet_count(&g, r->out, nullptr, nullptr, 0, st,
+                        (S->flags & ~GC_SERVE_NO_LANE) | GC_VALIDATE);
     if (rc != GC_OK) err = graphlet_last_error();
   }
   (void)hipStreamSynchronize(st);
@@ -242,6 +277,38 @@ void run_update(gc_server *S, Request *r, hipStream_t st) {
   finish(S, r, rc, err, 0);
 }
 
+// A count request by the single-graph path on stream st: upload, count, free.
+void count_one(gc_server *S, Request *r, hipStream_t st) {
+  int rc = GC_OK;
+  std::string err;
+  int32_t *d_rp = nullptr, *d_col = nullptr;
+  hipError_t e = hipMallocAsync((void **)&d_rp, sizeof(int32_t) * (r->n + 1), st);
+  if (e == hipSuccess && r->nnz > 0)
+    e = hipMallocAsync((void **)&d_col, sizeof(int32_t) * r->nnz, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_rp, r->rp.data(), sizeof(int32_t) * (r->n + 1), hipMemcpyHostToDevice,
+                       st);
+  if (e == hipSuccess && r->nnz > 0)
+    e = hipMemcpyAsync(d_col, r->col.data(), sizeof(int32_t) * r->nnz, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) {
+    rc = e == hipErrorOutOfMemory ? GC_ENOMEM : GC_EHIP;
+    err = hipGetErrorString(e);
+  } else {
+    gc_csr g{r->n, r->nnz, d_rp, d_col};
+    rc = graphlet_count(&g, r->out, nullptr, nullptr, 0, st, S->flags & ~GC_SERVE_NO_LANE);
+    if (rc != GC_OK) err = graphlet_last_error();
+  }
+  if (d_col) (void)hipFreeAsync(d_col, st);
+  if (d_rp) (void)hipFreeAsync(d_rp, st);
+  (void)hipStreamSynchronize(st);
+  finish(S, r, rc, err, 0);
+}
+
+// A count request for the batch lane (under the lock).
+bool is_small(const gc_server *S, const Request *r) {
+  return S->lane.on && r->kind == COUNT && r->n <= GC_BATCH_MAX_N && r->nnz <= kLaneEntries;
+}
+
 void worker_main(gc_server *S) {
   (void)hipSetDevice(S->device);
   hipStream_t st = nullptr;
@@ -257,6 +324,7 @@ void worker_main(gc_server *S) {
         // before it (the graph is busy meanwhile)
         for (auto it = S->pending.begin(); it != S->pending.end(); ++it) {
           Request *q = *it;
+          if (is_small(S, q)) continue;  // the batch lane's
           if (q->kind == UPDATE && (!q->g->ready || q->g->busy)) continue;
           if (S->in_use + q->footprint <= S->budget) {
             r = q;
@@ -283,32 +351,141 @@ void worker_main(gc_server *S) {
       run_update(S, r, st);
       continue;
     }
-    // run outside the lock
-    int rc = GC_OK;
-    std::string err;
-    int32_t *d_rp = nullptr, *d_col = nullptr;
-    hipError_t e = hipMallocAsync((void **)&d_rp, sizeof(int32_t) * (r->n + 1), st);
-    if (e == hipSuccess && r->nnz > 0)
-      e = hipMallocAsync((void **)&d_col, sizeof(int32_t) * r->nnz, st);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(d_rp, r->rp.data(), sizeof(int32_t) * (r->n + 1), hipMemcpyHostToDevice,
-                         st);
-    if (e == hipSuccess && r->nnz > 0)
-      e = hipMemcpyAsync(d_col, r->col.data(), sizeof(int32_t) * r->nnz, hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) {
-      rc = e == hipErrorOutOfMemory ? GC_ENOMEM : GC_EHIP;
-      err = hipGetErrorString(e);
-    } else {
-      gc_csr g{r->n, r->nnz, d_rp, d_col};
-      rc = graphlet_count(&g, r->out, nullptr, nullptr, 0, st, S->flags);
-      if (rc != GC_OK) err = graphlet_last_error();
-    }
-    if (d_col) (void)hipFreeAsync(d_col, st);
-    if (d_rp) (void)hipFreeAsync(d_rp, st);
-    (void)hipStreamSynchronize(st);
-    finish(S, r, rc, err, 0);
+    count_one(S, r, st);  // outside the lock
   }
   if (st) (void)hipStreamDestroy(st);
+}
+
+// The batch lane: every pending small request, up to the lane's capacity, in
+// one batched call on the lane's stream.
+void run_batch(gc_server *S, const std::vector<Request *> &take) {
+  Lane &L = S->lane;
+  const int G = (int)take.size();
+  int64_t rows = 0, ents = 0;
+  L.h_off[0] = 0;
+  L.h_rp[0] = 0;
+  for (int g = 0; g < G; g++) {
+    const Request *r = take[g];
+    for (int64_t i = 0; i < r->n; i++) L.h_rp[rows + i + 1] = (int32_t)(ents + r->rp[i + 1]);
+    if (r->nnz) std::memcpy(L.h_col + ents, r->col.data(), sizeof(int32_t) * (size_t)r->nnz);
+    rows += r->n;
+    ents += r->nnz;
+    L.h_off[g + 1] = rows;
+  }
+  hipError_t e = hipMemcpyAsync(L.d_off, L.h_off, sizeof(int64_t) * (G + 1),
+                                hipMemcpyHostToDevice, L.st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(L.d_rp, L.h_rp, sizeof(int32_t) * (rows + 1), hipMemcpyHostToDevice, L.st);
+  if (e == hipSuccess && ents)
+    e = hipMemcpyAsync(L.d_col, L.h_col, sizeof(int32_t) * ents, hipMemcpyHostToDevice, L.st);
+  int rc = e == hipSuccess ? GC_OK : GC_EHIP;
+  if (rc == GC_OK) {
+    gc_batch b{G, L.d_off, L.d_rp, L.d_col};
+    rc = graphlet_count_batched_noalloc(&b, L.d_out, L.st, S->flags & GC_VALIDATE);
+  }
+  if (rc == GC_OK) {
+    e = hipMemcpyAsync(L.h_out, L.d_out, sizeof(int64_t) * 17 * G, hipMemcpyDeviceToHost, L.st);
+    if (e == hipSuccess) e = hipStreamSynchronize(L.st);
+    if (e != hipSuccess) rc = GC_EHIP;
+  } else {
+    (void)hipStreamSynchronize(L.st);
+  }
+  if (rc == GC_OK) {
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->batches++;
+      S->batched += G;
+    }
+    for (int g = 0; g < G; g++) {
+      Request *r = take[g];
+      for (int k = 0; k < 17; k++) {
+        r->out[k].lo = (uint64_t)L.h_out[(size_t)g * 17 + k];  // non-negative
+        r->out[k].hi = 0;
+      }
+      finish(S, r, GC_OK, std::string(), 0);
+    }
+    return;
+  }
+  // a failed batch: each request again on its own, so an error stays with its
+  // request
+  for (Request *r : take) count_one(S, r, L.st);
+}
+
+void lane_main(gc_server *S) {
+  (void)hipSetDevice(S->device);
+  while (true) {
+    std::vector<Request *> take;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      while (true) {
+        if (S->stop) break;
+        int64_t rows = 0, ents = 0;
+        for (auto it = S->pending.begin(); it != S->pending.end();) {
+          Request *q = *it;
+          if (is_small(S, q) && (int)take.size() < kLaneGraphs && rows + q->n <= kLaneRows &&
+              ents + q->nnz <= kLaneEntries) {
+            rows += q->n;
+            ents += q->nnz;
+            take.push_back(q);
+            it = S->pending.erase(it);
+          } else {
+            ++it;
+          }
+        }
+        if (!take.empty()) break;
+        S->cv_lane.wait(lk);
+      }
+      if (take.empty()) break;
+      const auto now = Clock::now();
+      for (Request *q : take) {
+        q->state = RUNNING;
+        q->t_start = now;
+        q->footprint = 0;  // the lane's buffers are charged once, at creation
+        S->running++;
+      }
+    }
+    run_batch(S, take);
+  }
+}
+
+// Device and pinned host buffers of the batch lane, if the budget leaves
+// room for them beside requests (it takes at most a quarter of the budget).
+void lane_create(gc_server *S) {
+  Lane &L = S->lane;
+  const size_t dev = sizeof(int64_t) * (kLaneGraphs + 1) + sizeof(int32_t) * (kLaneRows + 1) +
+                     sizeof(int32_t) * kLaneEntries + sizeof(int64_t) * 17 * kLaneGraphs;
+  if ((S->flags & GC_SERVE_NO_LANE) || 4 * dev > S->budget) return;
+  hipError_t e = hipStreamCreateWithFlags(&L.st, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipMalloc((void **)&L.d_off, sizeof(int64_t) * (kLaneGraphs + 1));
+  if (e == hipSuccess) e = hipMalloc((void **)&L.d_rp, sizeof(int32_t) * (kLaneRows + 1));
+  if (e == hipSuccess) e = hipMalloc((void **)&L.d_col, sizeof(int32_t) * kLaneEntries);
+  if (e == hipSuccess) e = hipMalloc((void **)&L.d_out, sizeof(int64_t) * 17 * kLaneGraphs);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&L.h_off, sizeof(int64_t) * (kLaneGraphs + 1));
+  if (e == hipSuccess) e = hipHostMalloc((void **)&L.h_rp, sizeof(int32_t) * (kLaneRows + 1));
+  if (e == hipSuccess) e = hipHostMalloc((void **)&L.h_col, sizeof(int32_t) * kLaneEntries);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&L.h_out, sizeof(int64_t) * 17 * kLaneGraphs);
+  if (e == hipSuccess) {
+    L.on = true;
+    L.bytes = dev;
+    S->in_use += dev;
+    S->peak = std::max(S->peak, S->in_use);
+  } else {
+    (void)hipGetLastError();
+  }
+}
+
+void lane_destroy(gc_server *S) {
+  Lane &L = S->lane;
+  if (L.d_off) (void)hipFree(L.d_off);
+  if (L.d_rp) (void)hipFree(L.d_rp);
+  if (L.d_col) (void)hipFree(L.d_col);
+  if (L.d_out) (void)hipFree(L.d_out);
+  if (L.h_off) (void)hipHostFree(L.h_off);
+  if (L.h_rp) (void)hipHostFree(L.h_rp);
+  if (L.h_col) (void)hipHostFree(L.h_col);
+  if (L.h_out) (void)hipHostFree(L.h_out);
+  if (L.st) (void)hipStreamDestroy(L.st);
+  L = Lane();
 }
 
 double percentile(std::vector<double> v, double q) {
@@ -364,15 +541,20 @@ gc_server *gc_server_create(size_t hbm_budget, int slots, uint32_t flags) {
   S->slots = slots;
   S->flags = flags;
   if (hipGetDevice(&S->device) != hipSuccess) S->device = 0;
+  lane_create(S);
   try {
     for (int i = 0; i < slots; i++) S->workers.emplace_back(worker_main, S);
+    if (S->lane.on) S->lane_thread = std::thread(lane_main, S);
   } catch (...) {
     {
       std::lock_guard<std::mutex> lk(S->mu);
       S->stop = true;
     }
     S->cv_work.notify_all();
+    S->cv_lane.notify_all();
     for (auto &t : S->workers) t.join();
+    if (S->lane_thread.joinable()) S->lane_thread.join();
+    lane_destroy(S);
     delete S;
     t_srv_err = "could not start worker threads";
     return nullptr;
@@ -430,7 +612,8 @@ int64_t gc_server_submit(gc_server *S, int64_t n, int64_t nnz, const int32_t *ro
   S->all[r->id] = r;
   S->pending.push_back(r);
   S->submitted++;
-  S->cv_work.notify_one();
+  if (is_small(S, r)) S->cv_lane.notify_one();
+  else S->cv_work.notify_one();
   return r->id;
 }
 
@@ -541,6 +724,8 @@ int gc_server_stats(gc_server *S, gc_serve_stats *o) {
   o->cancelled = S->cancelled;
   o->pending = (int64_t)S->pending.size();
   o->running = S->running;
+  o->batches = S->batches;
+  o->batched = S->batched;
   o->bytes_in_use = S->in_use;
   o->bytes_peak = S->peak;
   o->budget = S->budget;
@@ -562,6 +747,7 @@ int gc_server_reset_stats(gc_server *S) {
   if (!S) return GC_EINVAL;
   std::lock_guard<std::mutex> lk(S->mu);
   S->submitted = S->completed = S->failed = S->rejected = S->cancelled = 0;
+  S->batches = S->batched = 0;
   S->edges_done = 0;
   S->latencies.clear();
   S->any = false;
@@ -727,9 +913,12 @@ void gc_server_destroy(gc_server *S) {
     S->pending.clear();
   }
   S->cv_work.notify_all();
+  S->cv_lane.notify_all();
   for (auto &t : S->workers) t.join();
+  if (S->lane_thread.joinable()) S->lane_thread.join();
   for (auto &kv : S->all) delete kv.second;
   (void)hipSetDevice(S->device);
+  lane_destroy(S);
   for (auto &kv : S->graphs) {
     free_resident(kv.second);
     delete kv.second;

@@ -44,6 +44,59 @@ def test_results_same_alone_and_in_the_mix():
         assert counts == oracle.identity_route(g)
 
 
+def small_graphs(count, seed):
+    """Graphs of at most 1024 vertices (the batch lane's), of mixed sizes and
+    densities, ER and torus random geometric."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(rng.integers(3, 1025))
+        if i % 5 == 4:
+            out.append(graphgen.rgg_torus(n, 8.0, int(rng.integers(1, 1 << 30))))
+        else:
+            m = int(rng.uniform(0.01, 0.3) * n * (n - 1) / 2)
+            out.append(graphgen.er_gnm(n, max(m, 1), int(rng.integers(1, 1 << 30))))
+    return out
+
+
+def test_small_graphs_batched_same_alone_and_in_the_mix():
+    # small graphs go to the batch lane, the others to the slots; every
+    # result equals the standalone single-graph call and the oracle
+    small = small_graphs(60, 505)
+    big = mixed_graphs(8, 506, m_max=300_000)
+    big = [g for g in big if g.n > gl.BATCH_MAX_N]
+    order = small[:20] + big + small[20:]
+    with gl.Server(budget_bytes=32 << 30, slots=4) as srv:
+        ids = [srv.submit(g.n, g.row_ptr, g.col) for g in order]
+        res = [srv.wait(i)[0] for i in ids]
+        st = srv.stats()
+    assert st["completed"] == len(order) and st["failed"] == 0
+    assert st["batches"] >= 1 and st["batched"] == len(small)
+    for g, counts in zip(order, res):
+        assert counts == standalone(g)
+    for g, counts in zip(order, res):
+        if g.n <= gl.BATCH_MAX_N:
+            assert counts == oracle.identity_route(g)
+
+
+def test_failed_batch_isolates_its_request():
+    # an asymmetric small graph in a burst of small graphs: under validation
+    # its batch fails and is counted again one request at a time, so only it
+    # fails
+    good = small_graphs(40, 507)
+    with gl.Server(budget_bytes=1 << 30, slots=2, validate=True) as srv:
+        ids = [srv.submit(g.n, g.row_ptr, g.col) for g in good[:20]]
+        bad = srv.submit(3, np.array([0, 1, 1, 2], np.int32), np.array([1, 0], np.int32))
+        ids += [srv.submit(g.n, g.row_ptr, g.col) for g in good[20:]]
+        with pytest.raises(gl.GraphletError) as e:
+            srv.wait(bad)
+        assert e.value.code == -4
+        for g, i in zip(good, ids):
+            assert srv.wait(i)[0] == standalone(g)
+        st = srv.stats()
+    assert st["failed"] == 1 and st["completed"] == len(good)
+
+
 def test_admission_never_exceeds_budget():
     graphs = mixed_graphs(16, 202, m_max=400_000)
     # budget about two of the largest footprints: requests must queue
@@ -53,11 +106,34 @@ def test_admission_never_exceeds_budget():
         rid = probe.submit(big.n, big.row_ptr, big.col)
         probe.wait(rid)
         budget = 2 * probe.stats()["bytes_peak"] + (1 << 20)
-    with gl.Server(budget_bytes=budget, slots=4) as srv:
-        ids = [srv.submit(g.n, g.row_ptr, g.col) for g in graphs]
-        res = [srv.wait(i) for i in ids]
-        st = srv.stats()
+    import threading
+
+    import torch
+
+    # the device's own free memory, sampled while the requests run: what the
+    # server holds never exceeds the budget (plus allocator rounding)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    low = [free0]
+    done = threading.Event()
+
+    def sample():
+        while not done.is_set():
+            low[0] = min(low[0], torch.cuda.mem_get_info()[0])
+            done.wait(0.0005)
+
+    t = threading.Thread(target=sample)
+    t.start()
+    try:
+        with gl.Server(budget_bytes=budget, slots=4) as srv:
+            ids = [srv.submit(g.n, g.row_ptr, g.col) for g in graphs]
+            res = [srv.wait(i) for i in ids]
+            st = srv.stats()
+    finally:
+        done.set()
+        t.join()
     assert st["bytes_peak"] <= budget
+    assert free0 - low[0] <= budget + (64 << 20), (free0 - low[0], budget)
     assert st["completed"] == len(graphs)
     for g, (counts, _) in zip(graphs, res):
         assert counts == standalone(g)
