@@ -386,8 +386,8 @@ __device__ __forceinline__ int band_chunk(int c0, int yb, int nL, const int32_t 
 
 // One heavy item in global mode by walking: list i of the item (the part of
 // N(v_i) below x) is owned by thread i mod block, at most LPT per thread, with
-// its cursor and the next PF entries in registers (nL <= kWalkLists, so the
-// run queue of kHeavyGroup entries holds every list).  Per chunk, each thread
+// its cursor and the next PF entries in registers (nL <= kWalkLists, and the
+// run queue holds every list).  Per chunk, each thread
 // counts the buffered entries below the chunk's end and reloads its buffer
 // from the new cursor (the loads of the next chunk are in flight while the
 // chunk is summed); a run that continues past the buffer takes up to three
@@ -398,11 +398,10 @@ __device__ __forceinline__ int band_chunk(int c0, int yb, int nL, const int32_t 
 // read.  Entries below the first counted rank (endpoints of degree <= 1,
 // which close no 4-cycle) are passed over in the first chunk.  Two or three
 // barriers per chunk, no global cursor state.
-template <int LPT>
-__device__ void heavy_walk_item(const C4Args &g, int Lx, int nL, int ya_item, int yb,
+template <int LPT, int PF, int XR>
+__device__ __forceinline__ void heavy_walk_item(const C4Args &g, int Lx, int nL, int ya_item, int yb,
                                 uint32_t *cnt, const int32_t *R, int32_t *qpos, int32_t *qend,
                                 int *s_nq, u128 &acc) {
-  constexpr int PF = 8, XR = 8;
   constexpr int NW = kC4HeavyBlock / kWave;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   const int ys = max(ya_item, R[4]);
@@ -571,7 +570,10 @@ __device__ void heavy_walk_item(const C4Args &g, int Lx, int nL, int ya_item, in
 template <bool PER_EDGE>
 __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
   __shared__ __align__(16) uint32_t cnt[kChunkWords];
-  __shared__ int32_t vpre[kHeavyGroup + 1], vcur[kHeavyGroup], sums[kC4HeavyBlock / kWave + 1];
+  // vpre / vcur: a group's run offsets and starts, or the walking path's run
+  // queue (a slot per list; global mode only)
+  constexpr int QL = PER_EDGE ? kHeavyGroup : kWalkLists;
+  __shared__ int32_t vpre[QL + 1], vcur[QL], sums[kC4HeavyBlock / kWave + 1];
   __shared__ int32_t vE[PER_EDGE ? kHeavyGroup : 1];
   __shared__ u64 red[32];
   __shared__ int s_item, s_nact, s_nsel, s_nq[2];
@@ -604,9 +606,11 @@ __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
     const int Lx = g.rp2[x], nL = g.lcnt[x];
     if (!PER_EDGE && nL <= kWalkLists) {  // the same on every thread
       if (nL <= kC4HeavyBlock)
-        heavy_walk_item<1>(g, Lx, nL, it.y, yb, cnt, s_R, vpre, vcur, s_nq, acc);
+        heavy_walk_item<1, 8, 8>(g, Lx, nL, it.y, yb, cnt, s_R, vpre, vcur, s_nq, acc);
+      else if (nL <= 2 * kC4HeavyBlock)
+        heavy_walk_item<2, 8, 8>(g, Lx, nL, it.y, yb, cnt, s_R, vpre, vcur, s_nq, acc);
       else
-        heavy_walk_item<2>(g, Lx, nL, it.y, yb, cnt, s_R, vpre, vcur, s_nq, acc);
+        heavy_walk_item<3, 8, 8>(g, Lx, nL, it.y, yb, cnt, s_R, vpre, vcur, s_nq, acc);
       continue;
     }
     // compact the lists with entries in [ya, yb)

@@ -51,11 +51,11 @@ constexpr int kChunkWords = 32768;
 constexpr int kC4HeavyBlock = 1024;
 constexpr int kHeavyGroup = 2048;
 // Heavy items (global mode) of vertices with at most this many lower
-// neighbours take the walking path (each thread owns up to two lists,
-// cursors in registers); long runs are queued for whole waves, and the
-// queue (kHeavyGroup entries) holds every list.
-constexpr int kWalkLists = 2 * kC4HeavyBlock;
-static_assert(kWalkLists <= kHeavyGroup, "the run queue holds every list");
+// neighbours take the walking path (each thread owns up to three lists,
+// cursors in registers); long runs are queued for whole waves, in a queue
+// with a slot per list.
+constexpr int kWalkLists = 3 * kC4HeavyBlock;
+static_assert(kWalkLists >= kHeavyGroup, "the group arrays share the queue's LDS");
 // Target wedges per heavy work item.
 constexpr u64 kPieceWork = u64(1) << 21;
 // Concurrent workgroups of the global-memory clique kernel.

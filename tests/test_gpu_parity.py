@@ -311,13 +311,13 @@ def test_dense_hub_slabs_rmat17():
 kDenseSlab = 256
 
 
-@pytest.mark.parametrize("nv", [700, 2000, 3000])
+@pytest.mark.parametrize("nv", [700, 2000, 3000, 4000])
 def test_heavy_items_long_runs(nv):
     # x is adjacent to nv vertices v, each adjacent to the same 30 vertices y
     # below x in the degree order (ties by id): every list of x's heavy item
     # has a run of 30 in one chunk, longer than a thread's buffer, so all nv
-    # lists go to the long-run queue together (one or two lists per thread up
-    # to 2048 lists; the general path above); the y's are heavy too, with
+    # lists go to the long-run queue together (one, two or three lists per
+    # thread up to 3072 lists; the general path above); the y's are heavy too, with
     # runs of every length up to 29
     ny = 30
     x = ny + nv
