@@ -15,7 +15,8 @@
 // (three rows ANDed), and 4-cycles come from the identity
 //   sum_e C4_e = 4 (C4ni - sum_e C(T_e, 2) + 3 K4),
 // where C4ni, the number of 4-cycles with chords allowed, is half the sum
-// over vertex pairs {a, b} of C(|N(a) n N(b)|, 2).  Step 3 accumulates the
+// over vertex pairs {a, b} of C(|N(a) n N(b)|, 2) (over all pairs for a dense
+// graph, over pairs two steps apart for a sparse one).  Step 3 accumulates the
 // unrestricted counts in int64 (every count of a graph with n <= 1024 fits)
 // and Step 4 applies the Lemmas of Section 4.3 on the device.
 #include <algorithm>
@@ -75,12 +76,15 @@ __device__ bool finalize_i64(const long long *A, long long n, long long m, long 
   return true;
 }
 
+// Registers held for 4 waves per SIMD at 512 threads and 5 at 256 (two
+// workgroups of 512 per compute unit when LDS allows).
 template <int WORDS, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_batched(const int64_t *node_off, const int32_t *rp,
-                                                   const int32_t *col, const int32_t *list,
-                                                   int count, int64_t *out, int32_t *err) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 512 ? 4 : 5)))
+void k_batched(const int64_t *node_off, const int32_t *rp, const int32_t *col,
+               const int32_t *list, int count, int64_t *out, int32_t *err) {
   extern __shared__ u64 R[];  // n * WORDS
   __shared__ long long red[BLOCK / kWave][kBAcc];
+  __shared__ unsigned long long s_sq;  // sum of squared degrees of the graph
   const int tid = threadIdx.x;
   for (int qi = blockIdx.x; qi < count; qi += gridDim.x) {
     const int64_t gi = list[qi];
@@ -93,15 +97,20 @@ __global__ __launch_bounds__(BLOCK) void k_batched(const int64_t *node_off, cons
     }
     const int64_t e0 = rp[r0];
     for (int w = tid; w < n * WORDS; w += BLOCK) R[w] = 0;
+    if (tid == 0) s_sq = 0;
     __syncthreads();
     // rows: each row written by one thread
+    unsigned long long sq = 0;
     for (int i = tid; i < n; i += BLOCK) {
       u64 *Ri = R + i * WORDS;
-      for (int64_t p = rp[r0 + i]; p < rp[r0 + i + 1]; p++) {
+      const int64_t pa = rp[r0 + i], pb = rp[r0 + i + 1];
+      for (int64_t p = pa; p < pb; p++) {
         const int j = col[p];
         Ri[j >> 6] |= 1ull << (j & 63);
       }
+      sq += (unsigned long long)((pb - pa) * (pb - pa));
     }
+    if (sq) atomicAdd(&s_sq, sq);
     __syncthreads();
     long long A[kBAcc];
 #pragma unroll
@@ -157,13 +166,38 @@ __global__ __launch_bounds__(BLOCK) void k_batched(const int64_t *node_off, cons
     }
     // 4-cycles with chords allowed: pairs {a, b} with c common neighbours
     // close C(c, 2) cycles on the diagonal a-b; each cycle has two diagonals.
-    for (int a = 0; a < n; a++) {
-      const u64 *Ra = R + a * WORDS;
-      for (int bb = a + 1 + tid; bb < n; bb += BLOCK) {
-        const u64 *Rb = R + bb * WORDS;
-        long long c = 0;
-        for (int w = 0; w < words; w++) c += __popcll(Ra[w] & Rb[w]);
-        A[B_C4NI] += ch2(c);
+    // Only pairs at distance two have c > 0.  A sparse graph takes, for each
+    // a, the union of its neighbours' rows (the vertices two steps away, a
+    // itself included) and the pairs with b > a in it: about
+    // sum_v deg(v)^2 row reads instead of n^2 / 2 (the same sum).
+    if (s_sq + (unsigned long long)nnz < (unsigned long long)n * (unsigned long long)n / 2) {
+      for (int a = tid; a < n; a += BLOCK) {
+        const u64 *Ra = R + a * WORDS;
+        const int64_t pa = rp[r0 + a], pb = rp[r0 + a + 1];
+        const int wa = (a + 1) >> 6;
+        for (int w = wa; w < words; w++) {  // a word of the union at a time
+          u64 t = 0;
+          for (int64_t p = pa; p < pb; p++) t |= R[col[p] * WORDS + w];
+          if (w == wa) t &= (~0ull) << ((a + 1) & 63);
+          while (t) {
+            const int b = (w << 6) + __ffsll((long long)t) - 1;
+            t &= t - 1;
+            const u64 *Rb = R + b * WORDS;
+            long long c = 0;
+            for (int z = 0; z < words; z++) c += __popcll(Ra[z] & Rb[z]);
+            A[B_C4NI] += ch2(c);
+          }
+        }
+      }
+    } else {
+      for (int a = 0; a < n; a++) {
+        const u64 *Ra = R + a * WORDS;
+        for (int bb = a + 1 + tid; bb < n; bb += BLOCK) {
+          const u64 *Rb = R + bb * WORDS;
+          long long c = 0;
+          for (int w = 0; w < words; w++) c += __popcll(Ra[w] & Rb[w]);
+          A[B_C4NI] += ch2(c);
+        }
       }
     }
     // block reduction
@@ -371,9 +405,13 @@ uint64_t signature(const std::vector<int64_t> &sizes) {
 // all-pairs pass and the 4-clique listing.
 double cost_of(int64_t n, int64_t nnz) {
   const double w = (double)((n + 63) / 64);
-  const double pairs = 0.5 * (double)n * (double)(n - 1);
+  // vertex pairs of the 4-cycle pass: all of them, or about sum deg^2 (taken
+  // as nnz^2 / n) for a sparse graph
+  const double all = 0.5 * (double)n * (double)(n - 1);
+  const double pairs =
+      std::min(all, n > 0 ? (double)nnz * (double)nnz / (double)n + (double)nnz : 0.0);
   const double rho = n > 1 ? (double)nnz / ((double)n * (double)(n - 1)) : 0.0;
-  const double tri = pairs * (double)(n - 2) / 3.0 * rho * rho * rho;
+  const double tri = all * (double)(n - 2) / 3.0 * rho * rho * rho;
   return pairs * w + 1.5 * tri * w + (double)nnz * (8.0 + w) + 2000.0;
 }
 
