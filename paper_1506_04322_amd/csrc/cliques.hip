@@ -163,7 +163,7 @@ __attribute__((amdgpu_waves_per_eu(BLOCK <= 512 ? 8 : 1))) void k_tk_up(TkArgs g
   // candidates per lane per slab, all loaded before any is probed; the
   // 1024-thread shape is held to 4 waves per SIMD by LDS, not registers, so
   // it keeps twice as many loads in flight
-  constexpr int RUN = BLOCK == 1024 ? 16 : 8;
+  constexpr int RUN = BLOCK == 1024 ? 16 : 6;
   // filter of U(u): 8 bits per hash slot (4 for the two largest tables),
   // so at most 1 in 32 candidates outside U(u) reaches the hash table
   constexpr int FLOG = (31 - __builtin_clz(HS)) + (HS <= 1024 ? 3 : 2);
@@ -227,27 +227,56 @@ __attribute__((amdgpu_waves_per_eu(BLOCK <= 512 ? 8 : 1))) void k_tk_up(TkArgs g
     const int total = P[nr];
     // Build: every entry x of U(U_i) that lies in U(u) is a triangle.  Each
     // thread takes RUN consecutive entries: positions first, then all loads,
-    // then the LDS work, so RUN reads are in flight per thread.
+    // then the filter, so RUN reads are in flight per thread.  The few
+    // candidates that pass the filter are packed, as candidate indices, into
+    // the wave's queue (the scan's scratch, free here) and probed 64 at a time,
+    // so the probe and the atomics run on full waves instead of once per
+    // candidate slot with most lanes idle; a queued index finds its row by
+    // binary search and its entry again (just read: a cache hit).
+    int32_t *qt = sums + (tid / kWave) * kWave;
+    int qn = 0;  // entries in the wave's queue (the same on every lane)
+    auto probe = [&](int cnt) {  // the queue's first cnt entries, one per lane
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const int l = lane_id();
+      if (l < cnt) {
+        const int t = qt[l];
+        const int o = upper_index_dev<int32_t>(P, nr, t);
+        const int pos = V[o] + (t - P[o]);
+        const int j = hfind(H, U, mask, hbits, g.col2[pos]);
+        if (j >= 0) {
+          const int ir = rid[o];
+          atomicOr(&R[tri_off(ir, W) + (j >> 6) - (ir >> 6)], 1ull << (j & 63));
+          atomicAdd(&colcnt[j], 1u);
+          atomicAdd(&g.T[pos], 1u);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
     int cursor = 0;  // row at or before the wave's next slab
     for (int s0 = (tid / kWave) * kWave * RUN; s0 < total; s0 += BLOCK * RUN) {
       int pos[RUN], row[RUN], xv[RUN];
       slab_positions<RUN>(P, V, rid, nr, total, s0, cursor, pos, row);
 #pragma unroll
-      for (int r = 0; r < RUN; r++) xv[r] = pos[r] >= 0 ? g.col2[pos[r]] : -1;
+      for (int r = 0; r < RUN; r++) xv[r] = g.col2[pos[r] >= 0 ? pos[r] : 0];
 #pragma unroll
       for (int r = 0; r < RUN; r++) {
-        if (pos[r] < 0) continue;
         const uint32_t f = fslot<FLOG>(xv[r]);
-        if (!((F[f >> 5] >> (f & 31)) & 1u)) continue;
-        const int j = hfind(H, U, mask, hbits, xv[r]);
-        if (j >= 0) {
-          const int ir = row[r];
-          atomicOr(&R[tri_off(ir, W) + (j >> 6) - (ir >> 6)], 1ull << (j & 63));
-          atomicAdd(&colcnt[j], 1u);
-          atomicAdd(&g.T[pos[r]], 1u);
+        const bool ok = pos[r] >= 0 && ((F[f >> 5] >> (f & 31)) & 1u);
+        const u64 b = __ballot(ok);
+        const int cnt = __popcll(b);
+        if (qn + cnt > kWave) {  // the same on every lane
+          probe(qn);
+          qn = 0;
         }
+        if (ok) qt[qn + __popcll(b & lanemask_lt())] = s0 + r * kWave + lane_id();
+        qn += cnt;
       }
     }
+    if (qn > 0) probe(qn);
     __syncthreads();
     // |Tri| of edges (u, U_i); 4-cliques u < U_i < U_j < U_l, each once.
     // Row i stays in registers (word z of the row, zero below word qi), so
