@@ -329,7 +329,7 @@ __attribute__((amdgpu_waves_per_eu(BLOCK <= 512 ? 8 : 1))) void k_tk_up(TkArgs g
 template <int BLOCK, int KCAP, int HS, bool GR, int KMIN = 0>
 __global__ __launch_bounds__(BLOCK) void k_tk_pe(TkArgs g) {
   constexpr int WC = (KCAP + 63) / 64;
-  constexpr int RUN = 8;
+  constexpr int RUN = 6;
   constexpr int FLOG = (31 - __builtin_clz(HS)) + (HS <= 1024 ? 3 : 2);  // as in k_tk_up
   constexpr int FW = (1 << FLOG) / 32;
   __shared__ int32_t U[KCAP], V[KCAP], P[KCAP + 1], rid[KCAP], H[HS], sums[BLOCK];
@@ -392,46 +392,70 @@ __global__ __launch_bounds__(BLOCK) void k_tk_pe(TkArgs g) {
     const int nr = nrows;
     block_scan_excl<BLOCK>(P, nr, sums);
     const int total = P[nr];
+    // Candidates past the bit filter are packed per wave (as candidate
+    // indices, in the scan's scratch) and probed 64 at a time, as in k_tk_up.
+    int32_t *qt = sums + (tid / kWave) * kWave;
     for (int pass = 0; pass < 2; pass++) {
+      int qn = 0;  // entries in the wave's queue (the same on every lane)
+      auto probe = [&](int cnt) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int l = lane_id();
+        if (l < cnt) {
+          const int t = qt[l];
+          const int o = upper_index_dev<int32_t>(P, nr, t);
+          const int p = V[o] + (t - P[o]);
+          const int j = hfind(H, U, mask, hbits, g.col2[p]);
+          const int ir = rid[o];  // j > ir: U(U_i) lies above U_i
+          if (j >= 0 && pass == 0) {
+            atomicOr(&R[(size_t)ir * W + (j >> 6)], 1ull << (j & 63));
+            atomicOr(&R[(size_t)j * W + (ir >> 6)], 1ull << (ir & 63));
+          } else if (j >= 0) {
+            const u64 *Ri = R + (size_t)ir * W, *Rj = R + (size_t)j * W;
+            uint32_t c = 0;
+            for (int z = 0; z < W; z++) c += (uint32_t)__popcll(Ri[z] & Rj[z]);
+            const u64 tij = g.T[p];
+            if (c) {
+              atomicAdd(&g.K4w[p], (u64)c);
+              atomicAdd(&A1[ir], c);
+              atomicAdd(&A1[j], c);
+            }
+            atomicAdd(&g.Dw[p], (u64)Tu[ir] + Tu[j] - 2);
+            atomicAdd(&A2[ir], (u64)Tu[j] + tij - 2);
+            atomicAdd(&A2[j], (u64)Tu[ir] + tij - 2);
+            if (g.Bw) {  // local vectors: degrees of the third vertex of the triangle
+              atomicAdd(&g.Bw[p], (u64)g.deg2[u]);
+              atomicAdd(&B2[ir], (u64)g.deg2[U[j]]);
+              atomicAdd(&B2[j], (u64)g.deg2[U[ir]]);
+            }
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      };
       int cursor = 0;  // row at or before the wave's next slab
       for (int s0 = (tid / kWave) * kWave * RUN; s0 < total; s0 += BLOCK * RUN) {
         int pos[RUN], row[RUN], xv[RUN];
         slab_positions<RUN>(P, V, rid, nr, total, s0, cursor, pos, row);
 #pragma unroll
-        for (int r = 0; r < RUN; r++) xv[r] = pos[r] >= 0 ? g.col2[pos[r]] : -1;
+        for (int r = 0; r < RUN; r++) xv[r] = g.col2[pos[r] >= 0 ? pos[r] : 0];
 #pragma unroll
         for (int r = 0; r < RUN; r++) {
-          if (pos[r] < 0) continue;
           const uint32_t f = fslot<FLOG>(xv[r]);
-          if (!((F[f >> 5] >> (f & 31)) & 1u)) continue;
-          const int j = hfind(H, U, mask, hbits, xv[r]);
-          if (j < 0) continue;
-          const int ir = row[r];  // j > ir: U(U_i) lies above U_i
-          if (pass == 0) {
-            atomicOr(&R[(size_t)ir * W + (j >> 6)], 1ull << (j & 63));
-            atomicOr(&R[(size_t)j * W + (ir >> 6)], 1ull << (ir & 63));
-            continue;
+          const bool ok = pos[r] >= 0 && ((F[f >> 5] >> (f & 31)) & 1u);
+          const u64 b = __ballot(ok);
+          const int cnt = __popcll(b);
+          if (qn + cnt > kWave) {  // the same on every lane
+            probe(qn);
+            qn = 0;
           }
-          const u64 *Ri = R + (size_t)ir * W, *Rj = R + (size_t)j * W;
-          uint32_t c = 0;
-          for (int z = 0; z < W; z++) c += (uint32_t)__popcll(Ri[z] & Rj[z]);
-          const int p = pos[r];
-          const u64 tij = g.T[p];
-          if (c) {
-            atomicAdd(&g.K4w[p], (u64)c);
-            atomicAdd(&A1[ir], c);
-            atomicAdd(&A1[j], c);
-          }
-          atomicAdd(&g.Dw[p], (u64)Tu[ir] + Tu[j] - 2);
-          atomicAdd(&A2[ir], (u64)Tu[j] + tij - 2);
-          atomicAdd(&A2[j], (u64)Tu[ir] + tij - 2);
-          if (g.Bw) {  // local vectors: degrees of the third vertex of the triangle
-            atomicAdd(&g.Bw[p], (u64)g.deg2[u]);
-            atomicAdd(&B2[ir], (u64)g.deg2[U[j]]);
-            atomicAdd(&B2[j], (u64)g.deg2[U[ir]]);
-          }
+          if (ok) qt[qn + __popcll(b & lanemask_lt())] = s0 + r * kWave + lane_id();
+          qn += cnt;
         }
       }
+      if (qn > 0) probe(qn);
       __syncthreads();
     }
     for (int i = tid; i < k; i += BLOCK) {
