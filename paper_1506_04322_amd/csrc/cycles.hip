@@ -275,7 +275,8 @@ __device__ __forceinline__ int count_below(const int32_t *col2, int p, int e, in
 // do not decrease with rank, so the counters of a chunk of low-degree
 // endpoints need few bits: a chunk's counters are 2^lb-bit fields packed
 // 2^(5-lb) to a 32-bit word (lb = 1: 2 bits, ..., lb = 5: 32 bits), and a
-// chunk is as wide as kChunkWords words of its fields, so the y range of an
+// chunk is as wide as CW words of its fields (kChunkWords, or kChunkWordsPE
+// in per-edge mode), so the y range of an
 // item is walked in fewer chunks where its endpoints have low degrees.  No
 // field can overflow into its neighbour.
 __device__ __forceinline__ void band_add(uint32_t *cnt, int lb, int d) {
@@ -333,10 +334,11 @@ __device__ __forceinline__ u64 band_quad_pairs(uint4 v, int lb) {
 }
 
 // This thread's share of the chunk's sum of C(c, 2), its counters cleared.
+template <int CW>
 __device__ __forceinline__ u64 band_sweep(uint32_t *cnt, int lb) {
   u64 part = 0;
   uint4 *c4 = reinterpret_cast<uint4 *>(cnt);
-  for (int w = threadIdx.x; w < kChunkWords / 4; w += blockDim.x) {
+  for (int w = threadIdx.x; w < CW / 4; w += blockDim.x) {
     const uint4 v = c4[w];
     if (v.x | v.y | v.z | v.w) {
       c4[w] = make_uint4(0u, 0u, 0u, 0u);
@@ -366,11 +368,12 @@ __device__ void band_ranks(const int32_t *deg2, int64_t n, int32_t *R) {
 
 // The next chunk [c0, c1) of an item and its field width 2^lb: the widest
 // chunk whose counters fit (the same on every thread).
+template <int CW>
 __device__ __forceinline__ int band_chunk(int c0, int yb, int nL, const int32_t *R, int *lb_out) {
   int64_t best = -1;
   int blb = 5;
   for (int lb = 1; lb <= 5; lb++) {
-    int64_t c1 = min((int64_t)yb, (int64_t)c0 + ((int64_t)kChunkWords << (5 - lb)));
+    int64_t c1 = min((int64_t)yb, (int64_t)c0 + ((int64_t)CW << (5 - lb)));
     if ((uint32_t)nL > band_mask(lb)) {
       if (c0 >= R[lb - 1]) continue;
       c1 = min(c1, (int64_t)R[lb - 1]);
@@ -384,10 +387,10 @@ __device__ __forceinline__ int band_chunk(int c0, int yb, int nL, const int32_t 
   return (int)best;
 }
 
-// One heavy item in global mode by walking: list i of the item (the part of
-// N(v_i) below x) is owned by thread i mod block, at most LPT per thread, with
-// its cursor and the next PF entries in registers (nL <= kWalkLists, and the
-// run queue holds every list).  Per chunk, each thread
+// One heavy item by walking: list i of the item (the part of N(v_i) below x)
+// is owned by thread i mod block, at most LPT per thread, with its cursor and
+// the next PF entries in registers (nL <= kWalkLists, kWalkListsPE in
+// per-edge mode, and the run queue holds every list).  Per chunk, each thread
 // counts the buffered entries below the chunk's end and reloads its buffer
 // from the new cursor (the loads of the next chunk are in flight while the
 // chunk is summed); a run that continues past the buffer takes up to three
@@ -396,12 +399,14 @@ __device__ __forceinline__ int band_chunk(int c0, int yb, int nL, const int32_t 
 // time, two rows of 64 consecutive entries of each per round.  The chunk's
 // counters are summed and cleared by a sweep of the LDS words, 16 bytes per
 // read.  Entries below the first counted rank (endpoints of degree <= 1,
-// which close no 4-cycle) are passed over in the first chunk.  Two or three
-// barriers per chunk, no global cursor state.
-template <int LPT, int PF, int XR>
-__device__ __forceinline__ void heavy_walk_item(const C4Args &g, int Lx, int nL, int ya_item, int yb,
-                                uint32_t *cnt, const int32_t *R, int32_t *qpos, int32_t *qend,
-                                int *s_nq, u128 &acc) {
+// which close no 4-cycle) are passed over in the first chunk.  Per-edge mode
+// (PE) credits each wedge once the chunk's counts are complete, before the
+// sweep.  Two to four barriers per chunk, no global cursor state.
+template <int LPT, int PF, int XR, bool PE, int CW>
+__device__ __forceinline__ void heavy_walk_item(const C4Args &g, int Lx, int nL, int ya_item,
+                                                int yb, uint32_t *cnt, const int32_t *R,
+                                                int32_t *qpos, int32_t *qend, int32_t *qstart,
+                                                int32_t *qid, int *s_nq, u128 &acc) {
   constexpr int NW = kC4HeavyBlock / kWave;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   const int ys = max(ya_item, R[4]);
@@ -427,12 +432,14 @@ __device__ __forceinline__ void heavy_walk_item(const C4Args &g, int Lx, int nL,
   int par = 0;
   for (int c0 = ys, c1; c0 < yb; c0 = c1, par ^= 1) {
     int lb;
-    c1 = band_chunk(c0, yb, nL, R, &lb);
+    c1 = band_chunk<CW>(c0, yb, nL, R, &lb);
     int qs[LPT];  // queue slot of a list whose run goes on past what it read, or -1
     int q[LPT];   // cursor after the entries read so far in this chunk
+    int ps[LPT];  // per-edge: the cursor at the chunk's start
     bool run[LPT];
 #pragma unroll
     for (int r = 0; r < LPT; r++) {
+      ps[r] = p[r];
       int taken = 0;
       bool live = true;
 #pragma unroll
@@ -484,6 +491,10 @@ __device__ __forceinline__ void heavy_walk_item(const C4Args &g, int Lx, int nL,
         const int slot = atomicAdd(&s_nq[par], 1);
         qpos[slot] = q[r];
         qend[slot] = e[r];
+        if (PE) {
+          qstart[slot] = q[r];
+          qid[slot] = tid + r * kC4HeavyBlock;
+        }
         qs[r] = slot;
       } else if (q[r] != p[r]) {
         p[r] = q[r];
@@ -547,14 +558,55 @@ __device__ __forceinline__ void heavy_walk_item(const C4Args &g, int Lx, int nL,
           for (int k = 0; k < PF; k++) buf[r][k] = p[r] + k < e[r] ? g.col2[p[r] + k] : INT32_MAX;
         }
     }
-    acc += (u128)band_sweep(cnt, lb);
+    if (PE) {
+      // The chunk's counts are complete: wedge x - v - y adds c(x, y) - 1 to
+      // edge (v, y) (v's entry for y) and, summed per list, to edge (x, v)
+      // (x's entry for v).  Each thread rereads its own part of its runs,
+      // each wave the queued parts it read.
+#pragma unroll
+      for (int r = 0; r < LPT; r++) {
+        u64 cr = 0;
+        for (int b = ps[r]; b < q[r]; b += PF) {
+          int yv[PF];
+#pragma unroll
+          for (int k = 0; k < PF; k++) yv[k] = b + k < q[r] ? g.col2[b + k] : -1;
+#pragma unroll
+          for (int k = 0; k < PF; k++) {
+            if (yv[k] < c0) continue;  // past the part, or below the first counted rank
+            const uint32_t c = band_get(cnt, lb, yv[k] - c0);
+            if (c >= 2) {
+              atomicAdd(&g.C4w[b + k], (u64)(c - 1));
+              cr += c - 1;
+            }
+          }
+        }
+        if (cr) atomicAdd(&g.C4w[Lx + tid + r * kC4HeavyBlock], cr);
+      }
+      for (int qi = wave; qi < nq; qi += NW) {
+        const int st = qstart[qi], en = qpos[qi];
+        u64 cr = 0;
+        for (int b = st + lane; b < en; b += kWave) {
+          const int y = g.col2[b];
+          if (y < c0) continue;
+          const uint32_t c = band_get(cnt, lb, y - c0);
+          if (c >= 2) {
+            atomicAdd(&g.C4w[b], (u64)(c - 1));
+            cr += c - 1;
+          }
+        }
+        cr = wave_sum_u64(cr);
+        if (lane == 0 && cr) atomicAdd(&g.C4w[Lx + qid[qi]], cr);
+      }
+      __syncthreads();  // the counters are read before the sweep clears them
+    }
+    acc += (u128)band_sweep<CW>(cnt, lb);
     __syncthreads();
   }
   __syncthreads();  // s_item is rewritten next
 }
 
-// Heavy x, balanced (global mode: vertices with more than kWalkLists lower
-// neighbours; per-edge mode: every heavy vertex).  Per item: the lower neighbours with at
+// Heavy x, balanced (vertices with more lower neighbours than the walking
+// path takes: kWalkLists, or kWalkListsPE in per-edge mode).  Per item: the lower neighbours with at
 // least one wedge in the item's y range are compacted (cursor, end, next
 // entry).  Per chunk: the lists whose next entry falls in the chunk are
 // selected by a coalesced pass over the next entries; in groups, the run of
@@ -569,12 +621,15 @@ __device__ __forceinline__ void heavy_walk_item(const C4Args &g, int Lx, int nL,
 // position afterwards).
 template <bool PER_EDGE>
 __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
-  __shared__ __align__(16) uint32_t cnt[kChunkWords];
-  // vpre / vcur: a group's run offsets and starts, or the walking path's run
-  // queue (a slot per list; global mode only)
-  constexpr int QL = PER_EDGE ? kHeavyGroup : kWalkLists;
+  constexpr int CW = PER_EDGE ? kChunkWordsPE : kChunkWords;
+  __shared__ __align__(16) uint32_t cnt[CW];
+  // vpre / vcur (and per-edge vE / vS): a group's run offsets, starts and
+  // entries, or the walking path's run queue (a slot per list: position,
+  // end, and per-edge the start and the list)
+  constexpr int QL = PER_EDGE ? kWalkListsPE : kWalkLists;
+  static_assert(QL >= kHeavyGroup, "the group arrays share the queue's LDS");
   __shared__ int32_t vpre[QL + 1], vcur[QL], sums[kC4HeavyBlock / kWave + 1];
-  __shared__ int32_t vE[PER_EDGE ? kHeavyGroup : 1];
+  __shared__ int32_t vE[PER_EDGE ? QL : 1], vS[PER_EDGE ? QL : 1];
   __shared__ u64 red[32];
   __shared__ int s_item, s_nact, s_nsel, s_nq[2];
   __shared__ int32_t s_R[5];
@@ -590,7 +645,7 @@ __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
   // current chunk
   int32_t *vid = PER_EDGE ? g.gvid + (size_t)blockIdx.x * g.lmax : nullptr;
   int32_t *cb = PER_EDGE ? g.gcb + (size_t)blockIdx.x * g.lmax : nullptr;
-  for (int w = tid; w < kChunkWords; w += kC4HeavyBlock) cnt[w] = 0;
+  for (int w = tid; w < CW; w += kC4HeavyBlock) cnt[w] = 0;
   u128 acc = 0;
   while (true) {
     if (tid == 0) {
@@ -604,13 +659,21 @@ __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
     const int x = it.x, yb = it.z;
     const int ya = max(it.y, s_R[4]);  // endpoints of degree <= 1 add nothing
     const int Lx = g.rp2[x], nL = g.lcnt[x];
-    if (!PER_EDGE && nL <= kWalkLists) {  // the same on every thread
-      if (nL <= kC4HeavyBlock)
-        heavy_walk_item<1, 8, 8>(g, Lx, nL, it.y, yb, cnt, s_R, vpre, vcur, s_nq, acc);
-      else if (nL <= 2 * kC4HeavyBlock)
-        heavy_walk_item<2, 8, 8>(g, Lx, nL, it.y, yb, cnt, s_R, vpre, vcur, s_nq, acc);
-      else
-        heavy_walk_item<3, 8, 8>(g, Lx, nL, it.y, yb, cnt, s_R, vpre, vcur, s_nq, acc);
+    if (nL <= QL) {  // the same on every thread
+      if (nL <= kC4HeavyBlock) {
+        heavy_walk_item<1, 8, 8, PER_EDGE, CW>(g, Lx, nL, it.y, yb, cnt, s_R, vpre, vcur, vS, vE,
+                                               s_nq, acc);
+      } else if constexpr (PER_EDGE) {
+        heavy_walk_item<2, 8, 8, true, CW>(g, Lx, nL, it.y, yb, cnt, s_R, vpre, vcur, vS, vE,
+                                           s_nq, acc);
+      } else {
+        if (nL <= 2 * kC4HeavyBlock)
+          heavy_walk_item<2, 8, 8, false, CW>(g, Lx, nL, it.y, yb, cnt, s_R, vpre, vcur, vS, vE,
+                                              s_nq, acc);
+        else
+          heavy_walk_item<3, 8, 8, false, CW>(g, Lx, nL, it.y, yb, cnt, s_R, vpre, vcur, vS, vE,
+                                              s_nq, acc);
+      }
       continue;
     }
     // compact the lists with entries in [ya, yb)
@@ -644,7 +707,7 @@ __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
     const int nA = s_nact;
     for (int c0 = ya, c1; c0 < yb; c0 = c1) {
       int lb;
-      c1 = band_chunk(c0, yb, nL, s_R, &lb);
+      c1 = band_chunk<CW>(c0, yb, nL, s_R, &lb);
       if (tid == 0) s_nsel = 0;
       __syncthreads();
       for (int b0 = 0; b0 < nA; b0 += kC4HeavyBlock) {
@@ -746,7 +809,7 @@ __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
           __syncthreads();
         }
       }
-      acc += (u128)band_sweep(cnt, lb);
+      acc += (u128)band_sweep<CW>(cnt, lb);
       __syncthreads();
     }
   }

@@ -48,6 +48,8 @@ constexpr int kMediumBlock = 1024;
 // Heavy wedge vertices: LDS counter chunk of 128 KiB; lower neighbours are
 // measured in groups of kHeavyGroup per chunk.
 constexpr int kChunkWords = 32768;
+// Per-edge mode: 112 KiB, leaving room for the run queue's four arrays.
+constexpr int kChunkWordsPE = 28672;
 constexpr int kC4HeavyBlock = 1024;
 constexpr int kHeavyGroup = 2048;
 // Heavy items (global mode) of vertices with at most this many lower
@@ -55,7 +57,7 @@ constexpr int kHeavyGroup = 2048;
 // cursors in registers); long runs are queued for whole waves, in a queue
 // with a slot per list.
 constexpr int kWalkLists = 3 * kC4HeavyBlock;
-static_assert(kWalkLists >= kHeavyGroup, "the group arrays share the queue's LDS");
+constexpr int kWalkListsPE = 2 * kC4HeavyBlock;  // per-edge mode: two lists per thread
 // Target wedges per heavy work item.
 constexpr u64 kPieceWork = u64(1) << 21;
 // Concurrent workgroups of the global-memory clique kernel.

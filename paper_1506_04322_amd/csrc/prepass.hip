@@ -131,34 +131,58 @@ __global__ void k_split_rows(const int32_t *rp2, const int32_t *col2, int64_t n,
   if (lane_id() == 0 && ce) atomicAdd(clique_entries, ce);
 }
 
-// tpos[p] = position of the reverse entry (x in the list of y).  Each
-// undirected edge is searched once, from its upper entry (y > x) in the
-// lower part of y's list, and both of its entries are written.  An upper
-// entry without a reverse, or a self-loop, is flagged (and keeps tpos[p] =
-// p).  If every search succeeds, distinct upper entries find distinct lower
-// entries; with as many lower entries as upper ones (checked by the first
-// thread) every lower entry is then written exactly once.
-__global__ void k_tpos(const u64 *ekeys, const int32_t *col2, const int32_t *rp2,
-                       const int32_t *lcnt, int64_t nnz, int B, const u64 *lower_total,
-                       int32_t *tpos, int32_t *err) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nnz) return;
-  if (p == 0 && 2 * *lower_total != (u64)nnz) flag_err(err, GC_EASYMMETRIC);
-  const int32_t x = (int32_t)(ekeys[p] >> B);
-  const int32_t y = col2[p];
-  if (y < x) return;  // written from its upper entry
-  if (y == x) {
-    flag_err(err, GC_ESELFLOOP);
-    return;
+// Twin positions (tpos[p] = position of the reverse entry) by a stable sort
+// instead of a search per edge.  Every upper entry p = (x, y), y >= x, gets
+// the key (y << 32 | p), written at its place among the upper entries in
+// CSR order (uoff: exclusive scan of |U|).  A stable sort on y then lists,
+// for each y, the upper entries pointing at y by increasing x: exactly the
+// order of the lower part of y's list, so the k-th of them is the twin of
+// y's k-th lower entry.  The pass after the sort checks each pairing (the
+// key's place lies in y's segment, loff: exclusive scan of |L|, and the
+// lower entry's value is the row of p), so a CSR that is not symmetric is
+// flagged, as is a self-loop (an upper entry y == x).
+__global__ void k_twin_keys(const int32_t *rp2, const int32_t *col2, const int32_t *ustart,
+                            const int32_t *uoff, int64_t n, u64 *keys, int32_t *err) {
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  const int lane = lane_id();
+  for (int64_t x = wave; x < n; x += nwaves) {
+    const int a = ustart[x], b = rp2[x + 1];
+    const int64_t o = (int64_t)uoff[x] - a;
+    for (int p = a + lane; p < b; p += kWave) {
+      const int32_t y = col2[p];
+      if (y == (int32_t)x) flag_err(err, GC_ESELFLOOP);
+      keys[o + p] = ((u64)(uint32_t)y << 32) | (u64)(uint32_t)p;
+    }
   }
-  const int a = rp2[y], len = lcnt[y];
-  const int q = a + lower_bound_dev<int32_t>(col2 + a, len, x);
-  if (q >= a + len || col2[q] != x) {
+}
+
+__global__ void k_twin_pairs(const u64 *sorted, int64_t nup, const int32_t *rp2,
+                             const int32_t *col2, const int32_t *lcnt, const int32_t *loff,
+                             int64_t n, int64_t nnz, const u64 *lower_total, int32_t *tpos,
+                             int32_t *err) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nup) return;
+  if (q == 0 && 2 * *lower_total != (u64)nnz) flag_err(err, GC_EASYMMETRIC);
+  const u64 key = sorted[q];
+  const int64_t y = (int64_t)(key >> 32), p = (int64_t)(key & 0xffffffffull);
+  if (y >= n || p >= nnz) {  // only with a count mismatch (keys left unwritten)
     flag_err(err, GC_EASYMMETRIC);
     return;
   }
-  tpos[p] = q;
-  tpos[q] = (int32_t)p;
+  const int64_t k = q - loff[y];
+  if (k < 0 || k >= lcnt[y]) {
+    flag_err(err, GC_EASYMMETRIC);
+    return;
+  }
+  const int32_t lo = rp2[y] + (int32_t)k;
+  const int32_t x = col2[lo];  // y's k-th lower neighbour: the row of p if symmetric
+  if (p < rp2[x] || p >= rp2[x + 1]) {
+    flag_err(err, GC_EASYMMETRIC);
+    return;
+  }
+  tpos[lo] = (int32_t)p;
+  tpos[p] = lo;
 }
 
 // W[x] = wedges x - v - y with v, y below x: sum over v in L(x) of the length
@@ -392,8 +416,27 @@ int run_prepass(PrepassArgs &p, Arena &a, hipStream_t s) {
   k_split_rows<<<grid1d(n, 256), 256, 0, s>>>(p.rp2, p.col2, n, p.lcnt, p.ucnt, p.ustart,
                                               &p.cnt->max_ucnt, &p.cnt->lower_total,
                                               &p.cnt->clique_entries);
-  k_tpos<<<grid1d(nnz, 256), 256, 0, s>>>(p.esorted, p.col2, p.rp2, p.lcnt, nnz, B,
-                                          &p.cnt->lower_total, p.tpos, &p.acc->err);
+  {
+    // twin positions: the upper entries sorted by target (the other edge-key
+    // buffer, free after the edge sort, holds the keys and their second
+    // buffer; the vertex-key buffers, free after the ranks, the offsets)
+    // upper entries if the CSR is symmetric (nnz is even); a CSR with another
+    // count is flagged by the count check, and its keys stay inside the
+    // buffer (at most nnz upper entries)
+    const int64_t nup = nnz / 2;
+    int32_t *uoff = reinterpret_cast<int32_t *>(p.rkeys);
+    int32_t *loff = reinterpret_cast<int32_t *>(p.rkeys_alt);
+    GC_TRY(scan_exclusive<int32_t>(p.ucnt, uoff, n, a, s));
+    GC_TRY(scan_exclusive<int32_t>(p.lcnt, loff, n, a, s));
+    u64 *tk = p.esorted == p.ekeys ? p.ekeys_alt : p.ekeys;
+    k_twin_keys<<<grid1d(n * kWave, 256, 65536), 256, 0, s>>>(p.rp2, p.col2, p.ustart, uoff, n, tk,
+                                                             &p.acc->err);
+    GC_TRY_HIP(hipGetLastError());
+    u64 *tsorted;
+    GC_TRY(radix_sort_u64(tk, tk + nup, nup, B, &tsorted, a, s, 32));
+    k_twin_pairs<<<grid1d(nup, 256), 256, 0, s>>>(tsorted, nup, p.rp2, p.col2, p.lcnt, loff, n,
+                                                 nnz, &p.cnt->lower_total, p.tpos, &p.acc->err);
+  }
   const unsigned wgrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 3) / 4, 16384));
   k_wedges<<<wgrid, 256, 0, s>>>(p.rp2, p.col2, p.lcnt, p.tpos, n, p.W);
   k_bins<<<grid1d(n, 256), 256, 0, s>>>(p.ucnt, p.lcnt, p.W, n, p.tk[0], p.tk[1], p.tk[2],

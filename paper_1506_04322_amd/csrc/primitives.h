@@ -10,11 +10,11 @@ namespace gc {
 template <class T>
 int scan_exclusive(const T *in, T *out, int64_t n, Arena &a, hipStream_t s);
 
-// Stable sort of 64-bit keys on bits [0, bits).  Sorts keys[0..n) using
-// alt[0..n) as the second buffer; returns the buffer that holds the result
-// (keys or alt) through *result.
+// Stable sort of 64-bit keys on bits [lo, lo + bits).  Sorts keys[0..n)
+// using alt[0..n) as the second buffer; returns the buffer that holds the
+// result (keys or alt) through *result.
 int radix_sort_u64(u64 *keys, u64 *alt, int64_t n, int bits, u64 **result, Arena &a,
-                   hipStream_t s);
+                   hipStream_t s, int lo = 0);
 
 // Fill n elements with a value (a kernel, never a memset node).
 template <class T>

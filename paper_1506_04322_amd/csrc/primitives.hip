@@ -171,7 +171,7 @@ template int fill<u64>(u64 *, u64, int64_t, hipStream_t);
 template int fill<int64_t>(int64_t *, int64_t, int64_t, hipStream_t);
 
 int radix_sort_u64(u64 *keys, u64 *alt, int64_t n, int bits, u64 **result, Arena &a,
-                   hipStream_t s) {
+                   hipStream_t s, int lo) {
   *result = keys;
   if (n <= 1 || bits <= 0) return GC_OK;
   const int64_t ntiles = (n + kRsTile - 1) / kRsTile;
@@ -184,7 +184,7 @@ int radix_sort_u64(u64 *keys, u64 *alt, int64_t n, int bits, u64 **result, Arena
   }
   if (a.overflow) return GC_ENOMEM;
   u64 *src = keys, *dst = alt;
-  for (int shift = 0; shift < bits; shift += 8) {
+  for (int shift = lo; shift < lo + bits; shift += 8) {
     k_rs_hist<<<(unsigned)ntiles, kRsBlock, 0, s>>>(src, n, shift, hist, ntiles);
     GC_TRY_HIP(hipGetLastError());
     GC_TRY(scan_exclusive<uint32_t>(hist, hist, ntiles * 256, a, s));

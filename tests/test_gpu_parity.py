@@ -332,6 +332,21 @@ def test_heavy_items_long_runs(nv):
         gl.graphlet_timing_enable(False)
     assert got == want
     assert t["heavy_items"] >= 2 and t["wedges_heavy"] >= nv * ny
+    # per-edge mode walks the same items and credits every wedge: the
+    # 17-vector, the sum rules and sampled edges (x's, the y's, others)
+    # against the literal per-edge oracle
+    got_pe, pe = gpu_counts(g, per_edge=True, validate=False)
+    assert got_pe == want
+    assert int(pe[0].sum()) == 3 * want[2] and int(pe[1].sum()) == 6 * want[6]
+    assert int(pe[2].sum()) == 4 * want[9]
+    eu, ev = oracle.edges(g)
+    rng = np.random.default_rng(nv)
+    idx = np.unique(np.concatenate([rng.integers(0, len(eu), 120),
+                                    np.nonzero(ev == x)[0][:40], np.nonzero(eu < ny)[0][:40]]))
+    T, K4, C4 = oracle.per_edge(g, eu[idx], ev[idx])
+    np.testing.assert_array_equal(pe[0][idx], T)
+    np.testing.assert_array_equal(pe[1][idx], K4)
+    np.testing.assert_array_equal(pe[2][idx], C4)
 
 
 # ------------------------------------------------------------ per-edge local vectors
