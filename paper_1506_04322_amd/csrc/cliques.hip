@@ -266,6 +266,19 @@ __attribute__((amdgpu_waves_per_eu(BLOCK <= 512 ? 8 : 1))) void k_tk_up(TkArgs g
       for (int r = 0; r < RUN; r++) {
         const uint32_t f = fslot<FLOG>(xv[r]);
         const bool ok = pos[r] >= 0 && ((F[f >> 5] >> (f & 31)) & 1u);
+        if (BLOCK == 1024) {
+          // the largest U(u) are dense: most slots pass, so probe in place
+          if (ok) {
+            const int j = hfind(H, U, mask, hbits, xv[r]);
+            if (j >= 0) {
+              const int ir = row[r];
+              atomicOr(&R[tri_off(ir, W) + (j >> 6) - (ir >> 6)], 1ull << (j & 63));
+              atomicAdd(&colcnt[j], 1u);
+              atomicAdd(&g.T[pos[r]], 1u);
+            }
+          }
+          continue;
+        }
         const u64 b = __ballot(ok);
         const int cnt = __popcll(b);
         if (qn + cnt > kWave) {  // the same on every lane

@@ -252,24 +252,6 @@ __global__ __launch_bounds__(kMediumBlock) void k_c4_medium(C4Args g) {
   if (threadIdx.x == 0 && s) atomic_add_u128(g.c4ni, s);
 }
 
-// Number of entries of the sorted run [p, e) below c1 (exponential then
-// binary search: about 2 log2(result) reads).
-__device__ __forceinline__ int count_below(const int32_t *col2, int p, int e, int c1) {
-  if (p >= e || col2[p] >= c1) return 0;
-  int lo = p, hi = p + 1, step = 1;  // col2[lo] < c1
-  while (hi < e && col2[hi] < c1) {
-    lo = hi;
-    step <<= 1;
-    hi = p + step;
-  }
-  if (hi > e) hi = e;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (col2[mid] < c1) lo = mid;
-    else hi = mid;
-  }
-  return hi - p;
-}
 
 // Counter bands of the heavy chunks.  c(x, y) <= min(nL, deg y), and degrees
 // do not decrease with rank, so the counters of a chunk of low-degree
@@ -605,213 +587,255 @@ __device__ __forceinline__ void heavy_walk_item(const C4Args &g, int Lx, int nL,
   __syncthreads();  // s_item is rewritten next
 }
 
-// Heavy x, balanced (vertices with more lower neighbours than the walking
-// path takes: kWalkLists, or kWalkListsPE in per-edge mode).  Per item: the lower neighbours with at
-// least one wedge in the item's y range are compacted (cursor, end, next
-// entry).  Per chunk: the lists whose next entry falls in the chunk are
-// selected by a coalesced pass over the next entries; in groups, the run of
-// each selected list inside the chunk is measured, then the runs are read
-// flat, so threads share long and short lists evenly and neighbouring
-// threads read neighbouring entries (in the last chunk below x a run is the
-// rest of its list, with no search).  Counters are zero between chunks: a
-// sweep sums and clears them.
-// Per-edge mode revisits each chunk's wedges once its counts are complete
-// (before they are cleared): wedge x - v - y adds c(x, y) - 1 to edge (v, y)
-// and to edge (x, v), each at a directed entry (folded into the edge's upper
-// position afterwards).
+// One heavy item with more lists than the registers of the walking path hold:
+// the same walk, over groups of 2 x block lists in turn within each chunk,
+// each list's cursor and end kept in the workgroup's slot of global memory
+// (cur, end) between groups and chunks, and its first PF entries read when
+// its group comes up.  The run queue is emptied per group.
+template <bool PE, int CW>
+__device__ __forceinline__ void heavy_walk_groups(const C4Args &g, int Lx, int nL, int ya_item,
+                                                  int yb, uint32_t *cnt, const int32_t *R,
+                                                  int32_t *qpos, int32_t *qend, int32_t *qstart,
+                                                  int32_t *qid, int *s_nq, int32_t *cur,
+                                                  int32_t *end, int32_t *cb, u128 &acc) {
+  constexpr int LPT = 2, PF = 8, XR = 8, GS = LPT * kC4HeavyBlock;
+  constexpr int NW = kC4HeavyBlock / kWave;
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+  const int ys = max(ya_item, R[4]);
+  for (int i = tid; i < nL; i += kC4HeavyBlock) {
+    const int q = Lx + i;
+    const int s = g.rp2[g.col2[q]];
+    const int e = g.tpos[q];
+    cur[i] = ya_item > 0 ? s + lower_bound_dev<int32_t>(g.col2 + s, e - s, ys) : s;
+    end[i] = e;
+  }
+  if (tid == 0) s_nq[0] = s_nq[1] = 0;
+  __syncthreads();
+  int par = 0;
+  for (int c0 = ys, c1; c0 < yb; c0 = c1) {
+    int lb;
+    c1 = band_chunk<CW>(c0, yb, nL, R, &lb);
+    for (int g0 = 0; g0 < nL; g0 += GS, par ^= 1) {
+      int p[LPT], e[LPT], q[LPT], qs[LPT];
+      bool run[LPT];
+      int buf[LPT][PF];
+#pragma unroll
+      for (int r = 0; r < LPT; r++) {
+        const int i = g0 + tid + r * kC4HeavyBlock;
+        p[r] = i < nL ? cur[i] : 0;
+        e[r] = i < nL ? end[i] : 0;
+        if (PE && i < nL) cb[i] = p[r];  // where the list's run in this chunk starts
+      }
+#pragma unroll
+      for (int r = 0; r < LPT; r++)
+#pragma unroll
+        for (int k = 0; k < PF; k++) buf[r][k] = p[r] + k < e[r] ? g.col2[p[r] + k] : INT32_MAX;
+#pragma unroll
+      for (int r = 0; r < LPT; r++) {
+        int taken = 0;
+        bool live = true;
+#pragma unroll
+        for (int k = 0; k < PF; k++) {
+          live = live && buf[r][k] < c1;
+          if (live) {
+            if (buf[r][k] >= c0) band_add(cnt, lb, buf[r][k] - c0);
+            taken++;
+          }
+        }
+        q[r] = p[r] + taken;
+        run[r] = taken == PF && q[r] < e[r];
+      }
+#pragma unroll
+      for (int round = 0; round < 3; round++) {
+        bool any = false;
+#pragma unroll
+        for (int r = 0; r < LPT; r++) any = any || run[r];
+        if (!any) break;
+        int yv[LPT][XR];
+#pragma unroll
+        for (int r = 0; r < LPT; r++)
+#pragma unroll
+          for (int k = 0; k < XR; k++)
+            yv[r][k] = run[r] && q[r] + k < e[r] ? g.col2[q[r] + k] : INT32_MAX;
+#pragma unroll
+        for (int r = 0; r < LPT; r++) {
+          int t = 0;
+          bool lv = run[r];
+#pragma unroll
+          for (int k = 0; k < XR; k++) {
+            lv = lv && yv[r][k] < c1;
+            if (lv) {
+              if (yv[r][k] >= c0) band_add(cnt, lb, yv[r][k] - c0);
+              t++;
+            }
+          }
+          q[r] += t;
+          run[r] = run[r] && t == XR && q[r] < e[r];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < LPT; r++) {
+        const int i = g0 + tid + r * kC4HeavyBlock;
+        qs[r] = -1;
+        if (run[r]) {
+          const int slot = atomicAdd(&s_nq[par], 1);  // at most GS per group
+          qpos[slot] = q[r];
+          qend[slot] = e[r];
+          qs[r] = slot;
+        } else if (i < nL && q[r] != p[r]) {
+          cur[i] = q[r];
+        }
+      }
+      __syncthreads();
+      const int nq = s_nq[par];
+      if (tid == 0) s_nq[par ^ 1] = 0;  // the next group's queue
+      if (nq > 0) {  // the same on every thread
+        for (int qi = wave; qi < nq; qi += NW) {
+          int pos = qpos[qi];
+          const int qe = qend[qi];
+          while (true) {  // every exit is decided by a ballot: the same on the wave
+            const int p0 = pos + lane, p1 = pos + kWave + lane;
+            const int y0 = p0 < qe ? g.col2[p0] : INT32_MAX;
+            const int y1 = p1 < qe ? g.col2[p1] : INT32_MAX;
+            const bool in0 = y0 < c1, in1 = y1 < c1;
+            if (in0 && y0 >= c0) band_add(cnt, lb, y0 - c0);
+            if (in1 && y1 >= c0) band_add(cnt, lb, y1 - c0);
+            const u64 b0 = __ballot(!in0), b1 = __ballot(!in1);
+            if (b0) {
+              pos += __ffsll((long long)b0) - 1;
+              break;
+            }
+            if (b1) {
+              pos += kWave + __ffsll((long long)b1) - 1;
+              break;
+            }
+            pos += 2 * kWave;
+          }
+          if (lane == 0) qpos[qi] = pos;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < LPT; r++)
+          if (qs[r] >= 0) cur[g0 + tid + r * kC4HeavyBlock] = qpos[qs[r]];
+      }
+      __syncthreads();  // the queue is rewritten by the next group
+    }
+    if (PE) {
+      // The chunk's counts are complete: each list's run in it is
+      // [cb, cur).  Group by group, a thread credits the short runs of its
+      // lists itself and queues the longer ones for whole waves.
+      for (int g0 = 0; g0 < nL; g0 += GS, par ^= 1) {
+#pragma unroll
+        for (int r = 0; r < LPT; r++) {
+          const int i = g0 + tid + r * kC4HeavyBlock;
+          if (i >= nL) continue;
+          const int st = cb[i], en = cur[i];
+          if (en - st > PF + 3 * XR) {
+            const int slot = atomicAdd(&s_nq[par], 1);
+            qstart[slot] = st;
+            qpos[slot] = en;
+            qid[slot] = i;
+            continue;
+          }
+          u64 cr = 0;
+          for (int b = st; b < en; b += PF) {
+            int yv[PF];
+#pragma unroll
+            for (int k = 0; k < PF; k++) yv[k] = b + k < en ? g.col2[b + k] : -1;
+#pragma unroll
+            for (int k = 0; k < PF; k++) {
+              if (yv[k] < c0) continue;  // past the run, or below the first counted rank
+              const uint32_t c = band_get(cnt, lb, yv[k] - c0);
+              if (c >= 2) {
+                atomicAdd(&g.C4w[b + k], (u64)(c - 1));
+                cr += c - 1;
+              }
+            }
+          }
+          if (cr) atomicAdd(&g.C4w[Lx + i], cr);
+        }
+        __syncthreads();
+        const int nq = s_nq[par];
+        if (tid == 0) s_nq[par ^ 1] = 0;
+        for (int qi = wave; qi < nq; qi += NW) {
+          const int st = qstart[qi], en = qpos[qi];
+          u64 cr = 0;
+          for (int b = st + lane; b < en; b += kWave) {
+            const int y = g.col2[b];
+            if (y < c0) continue;
+            const uint32_t c = band_get(cnt, lb, y - c0);
+            if (c >= 2) {
+              atomicAdd(&g.C4w[b], (u64)(c - 1));
+              cr += c - 1;
+            }
+          }
+          cr = wave_sum_u64(cr);
+          if (lane == 0 && cr) atomicAdd(&g.C4w[Lx + qid[qi]], cr);
+        }
+        __syncthreads();  // the queue is rewritten by the next group
+      }
+    }
+    acc += (u128)band_sweep<CW>(cnt, lb);
+    __syncthreads();
+  }
+  __syncthreads();  // s_item is rewritten next
+}
+
+// Heavy x: work items (x, y range) taken from a queue, one workgroup each,
+// walked chunk by chunk (heavy_walk_item, or heavy_walk_groups for more
+// lists than the registers hold).  In per-edge mode each wedge x - v - y
+// adds c(x, y) - 1 to edge (v, y) and to edge (x, v), each at a directed
+// entry (folded into the edge's upper position afterwards).
 template <bool PER_EDGE>
 __global__ __launch_bounds__(kC4HeavyBlock) void k_c4_heavy_bal(C4Args g) {
   constexpr int CW = PER_EDGE ? kChunkWordsPE : kChunkWords;
   __shared__ __align__(16) uint32_t cnt[CW];
-  // vpre / vcur (and per-edge vE / vS): a group's run offsets, starts and
-  // entries, or the walking path's run queue (a slot per list: position,
-  // end, and per-edge the start and the list)
+  // the run queue, a slot per list of a walk or a group: position and end,
+  // and per-edge the start and the list
   constexpr int QL = PER_EDGE ? kWalkListsPE : kWalkLists;
-  static_assert(QL >= kHeavyGroup, "the group arrays share the queue's LDS");
-  __shared__ int32_t vpre[QL + 1], vcur[QL], sums[kC4HeavyBlock / kWave + 1];
-  __shared__ int32_t vE[PER_EDGE ? QL : 1], vS[PER_EDGE ? QL : 1];
+  static_assert(QL >= 2 * kC4HeavyBlock, "a group's lists fit the queue");
+  __shared__ int32_t qpos[QL], qend[QL];
+  __shared__ int32_t qid[PER_EDGE ? QL : 1], qstart[PER_EDGE ? QL : 1];
   __shared__ u64 red[32];
-  __shared__ int s_item, s_nact, s_nsel, s_nq[2];
+  __shared__ int s_item, s_nq[2];
   __shared__ int32_t s_R[5];
-  constexpr int RUN = 8;
   const int tid = threadIdx.x;
   band_ranks(g.deg2, g.n, s_R);
   const int64_t nitems = *g.nitems;
+  // per-slot list state of heavy_walk_groups: cursor, end, and per-edge the
+  // cursor where the current chunk began
   int32_t *cur = g.gcur + (size_t)blockIdx.x * g.lmax;
   int32_t *end = g.gbeg + (size_t)blockIdx.x * g.lmax;
-  int32_t *nxt = g.gnext + (size_t)blockIdx.x * g.lmax;
-  int32_t *sel = g.gsel + (size_t)blockIdx.x * g.lmax;
-  // per-edge: list index of each active list and its run start in the
-  // current chunk
-  int32_t *vid = PER_EDGE ? g.gvid + (size_t)blockIdx.x * g.lmax : nullptr;
   int32_t *cb = PER_EDGE ? g.gcb + (size_t)blockIdx.x * g.lmax : nullptr;
   for (int w = tid; w < CW; w += kC4HeavyBlock) cnt[w] = 0;
   u128 acc = 0;
   while (true) {
-    if (tid == 0) {
-      s_item = (int)atomicAdd(g.queue, 1ull);
-      s_nact = 0;
-    }
+    if (tid == 0) s_item = (int)atomicAdd(g.queue, 1ull);
     __syncthreads();
     const int item = s_item;
     if (item >= nitems) break;
     const int4 it = g.items[item];
     const int x = it.x, yb = it.z;
-    const int ya = max(it.y, s_R[4]);  // endpoints of degree <= 1 add nothing
     const int Lx = g.rp2[x], nL = g.lcnt[x];
     if (nL <= QL) {  // the same on every thread
       if (nL <= kC4HeavyBlock) {
-        heavy_walk_item<1, 8, 8, PER_EDGE, CW>(g, Lx, nL, it.y, yb, cnt, s_R, vpre, vcur, vS, vE,
-                                               s_nq, acc);
+        heavy_walk_item<1, 8, 8, PER_EDGE, CW>(g, Lx, nL, it.y, yb, cnt, s_R, qpos, qend, qstart,
+                                               qid, s_nq, acc);
       } else if constexpr (PER_EDGE) {
-        heavy_walk_item<2, 8, 8, true, CW>(g, Lx, nL, it.y, yb, cnt, s_R, vpre, vcur, vS, vE,
+        heavy_walk_item<2, 8, 8, true, CW>(g, Lx, nL, it.y, yb, cnt, s_R, qpos, qend, qstart, qid,
                                            s_nq, acc);
       } else {
         if (nL <= 2 * kC4HeavyBlock)
-          heavy_walk_item<2, 8, 8, false, CW>(g, Lx, nL, it.y, yb, cnt, s_R, vpre, vcur, vS, vE,
-                                              s_nq, acc);
+          heavy_walk_item<2, 8, 8, false, CW>(g, Lx, nL, it.y, yb, cnt, s_R, qpos, qend, qstart,
+                                              qid, s_nq, acc);
         else
-          heavy_walk_item<3, 8, 8, false, CW>(g, Lx, nL, it.y, yb, cnt, s_R, vpre, vcur, vS, vE,
-                                              s_nq, acc);
+          heavy_walk_item<3, 8, 8, false, CW>(g, Lx, nL, it.y, yb, cnt, s_R, qpos, qend, qstart,
+                                              qid, s_nq, acc);
       }
       continue;
     }
-    // compact the lists with entries in [ya, yb)
-    for (int b0 = 0; b0 < nL; b0 += kC4HeavyBlock) {
-      const int i = b0 + tid;
-      int c = 0, e = 0, y = 0;
-      bool act = false;
-      if (i < nL) {
-        const int q = Lx + i;
-        const int s = g.rp2[g.col2[q]];
-        e = g.tpos[q];
-        c = s + lower_bound_dev<int32_t>(g.col2 + s, e - s, ya);
-        if (c < e) {
-          y = g.col2[c];
-          act = y < yb;
-        }
-      }
-      const u64 mask = __ballot(act);
-      int base = 0;
-      if (lane_id() == 0 && mask) base = atomicAdd(&s_nact, __popcll(mask));
-      base = __shfl(base, 0, kWave);
-      if (act) {
-        const int o = base + __popcll(mask & lanemask_lt());
-        cur[o] = c;
-        end[o] = e;
-        nxt[o] = y;
-        if (PER_EDGE) vid[o] = i;
-      }
-    }
-    __syncthreads();
-    const int nA = s_nact;
-    for (int c0 = ya, c1; c0 < yb; c0 = c1) {
-      int lb;
-      c1 = band_chunk<CW>(c0, yb, nL, s_R, &lb);
-      if (tid == 0) s_nsel = 0;
-      __syncthreads();
-      for (int b0 = 0; b0 < nA; b0 += kC4HeavyBlock) {
-        const int i = b0 + tid;
-        const bool in = i < nA && nxt[i] < c1;
-        const u64 mask = __ballot(in);
-        int base = 0;
-        if (lane_id() == 0 && mask) base = atomicAdd(&s_nsel, __popcll(mask));
-        base = __shfl(base, 0, kWave);
-        if (in) sel[base + __popcll(mask & lanemask_lt())] = i;
-      }
-      __syncthreads();
-      const int nS = s_nsel;
-      if (nS == 0) continue;  // uniform: no wedge of this item in the chunk
-      for (int g0 = 0; g0 < nS; g0 += kHeavyGroup) {
-        const int nG = min(kHeavyGroup, nS - g0);
-        for (int j = tid; j < nG; j += kC4HeavyBlock) {
-          const int i = sel[g0 + j];
-          const int p = cur[i];
-          vcur[j] = p;
-          // the last chunk below x: every entry left in the list is in it
-          vpre[j] = c1 >= x ? end[i] - p : count_below(g.col2, p, end[i], c1);
-        }
-        __syncthreads();
-        scan_excl<kC4HeavyBlock>(vpre, nG, sums);
-        const int F = vpre[nG];
-        for (int f0 = tid * RUN; f0 < F; f0 += kC4HeavyBlock * RUN) {
-          int j = upper_index_dev<int32_t>(vpre, nG, f0);
-          int pos[RUN], yv[RUN];
-#pragma unroll
-          for (int r = 0; r < RUN; r++) {
-            const int f = f0 + r;
-            pos[r] = -1;
-            if (f < F) {
-              while (vpre[j + 1] <= f) j++;
-              pos[r] = vcur[j] + (f - vpre[j]);
-            }
-          }
-#pragma unroll
-          for (int r = 0; r < RUN; r++) yv[r] = pos[r] >= 0 ? g.col2[pos[r]] : 0;
-#pragma unroll
-          for (int r = 0; r < RUN; r++) {
-            if (pos[r] < 0) continue;
-            band_add(cnt, lb, yv[r] - c0);
-          }
-        }
-        for (int j = tid; j < nG; j += kC4HeavyBlock) {
-          const int i = sel[g0 + j];
-          const int p = vcur[j] + (vpre[j + 1] - vpre[j]);
-          if (PER_EDGE) cb[i] = vcur[j];
-          cur[i] = p;
-          nxt[i] = p < end[i] ? g.col2[p] : INT32_MAX;
-        }
-        __syncthreads();
-      }
-      if (PER_EDGE) {
-        // The chunk's counts are complete: credit its wedges, group by group
-        // (the last group leaves vcur / vpre as the counting pass did).
-        // Consecutive threads take consecutive wedges, so the credits of a
-        // run land on consecutive entries; the credits of edge (x, v) are
-        // summed over each wave's run of v first.
-        for (int g0 = 0; g0 < nS; g0 += kHeavyGroup) {
-          const int nG = min(kHeavyGroup, nS - g0);
-          for (int j = tid; j < nG; j += kC4HeavyBlock) {
-            const int i = sel[g0 + j];
-            vcur[j] = cb[i];
-            vpre[j] = cur[i] - cb[i];
-            vE[j] = Lx + vid[i];
-          }
-          __syncthreads();
-          scan_excl<kC4HeavyBlock>(vpre, nG, sums);
-          const int F = vpre[nG];
-          for (int f0 = 0; f0 < F; f0 += kC4HeavyBlock) {
-            const int f = f0 + tid;
-            int j = -1;
-            u64 cr = 0;
-            if (f < F) {
-              j = upper_index_dev<int32_t>(vpre, nG, f);
-              const int p = vcur[j] + (f - vpre[j]);
-              const uint32_t c = band_get(cnt, lb, g.col2[p] - c0);
-              if (c >= 2) {
-                cr = c - 1;
-                atomicAdd(&g.C4w[p], cr);  // edge (v, y) at v's entry for y
-              }
-            }
-            // segmented sum over the wave's lanes with the same list (lanes
-            // hold increasing f, so each list is a contiguous run of lanes)
-            const int lane = lane_id();
-#pragma unroll
-            for (int off = 1; off < kWave; off <<= 1) {
-              const u64 o = __shfl_up(cr, off, kWave);
-              const int jo = __shfl_up(j, off, kWave);
-              if (lane >= off && jo == j) cr += o;
-            }
-            const int jn = __shfl_down(j, 1, kWave);
-            if (j >= 0 && cr && (lane == kWave - 1 || jn != j))
-              atomicAdd(&g.C4w[vE[j]], cr);  // edge (x, v) at x's entry for v
-          }
-          __syncthreads();
-        }
-      }
-      acc += (u128)band_sweep<CW>(cnt, lb);
-      __syncthreads();
-    }
+    heavy_walk_groups<PER_EDGE, CW>(g, Lx, nL, it.y, yb, cnt, s_R, qpos, qend, qstart, qid, s_nq,
+                                    cur, end, cb, acc);
   }
   const u128 s = block_sum_u128(acc, red);
   if (threadIdx.x == 0 && s) atomic_add_u128(g.c4ni, s);

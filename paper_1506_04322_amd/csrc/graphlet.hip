@@ -130,7 +130,7 @@ struct Dyn {
   u64 *gR;
   int32_t *gI;
   u64 *gA;
-  int32_t *gcur, *gbeg, *gnext, *gsel, *gvid, *gcb;
+  int32_t *gcur, *gbeg, *gcb;
   int4 *items;
   u64 *hkeys, *hkeys_alt;
   int64_t *pcount;
@@ -147,9 +147,6 @@ void alloc_dyn(Arena &a, const Plan &P, const DynNeed &d, Dyn &y) {
   const size_t lm = (size_t)std::max(d.lmax, 1), sl = (size_t)std::max(d.slots, 1);
   y.gcur = a.take<int32_t>(sl * lm);
   y.gbeg = a.take<int32_t>(sl * lm);
-  y.gnext = a.take<int32_t>(sl * lm);
-  y.gsel = a.take<int32_t>(sl * lm);
-  y.gvid = P.per_edge ? a.take<int32_t>(sl * lm) : nullptr;
   y.gcb = P.per_edge ? a.take<int32_t>(sl * lm) : nullptr;
   y.items = a.take<int4>((size_t)std::max<int64_t>(d.items_cap, 1));
   const size_t nh = (size_t)std::max(d.nheavy, 1);
@@ -532,9 +529,6 @@ int run(const gc_csr *G, gc_u128 out17[17], int64_t *per_edge_out, int64_t *loca
     c4.queue = &pp.acc->queue;
     c4.gcur = dy.gcur;
     c4.gbeg = dy.gbeg;
-    c4.gnext = dy.gnext;
-    c4.gsel = dy.gsel;
-    c4.gvid = dy.gvid;
     c4.gcb = dy.gcb;
     c4.lmax = std::max(dn.lmax, 1);
     GC_TRY(launch_cycles_heavy(c4, dn.slots, P.per_edge, s));

@@ -45,17 +45,16 @@ constexpr int kHashSlots = 2048;
 constexpr u64 kMediumWedges = 16384;
 constexpr int kMediumSlots = 22528;
 constexpr int kMediumBlock = 1024;
-// Heavy wedge vertices: LDS counter chunk of 128 KiB; lower neighbours are
-// measured in groups of kHeavyGroup per chunk.
+// Heavy wedge vertices: LDS counter chunk of 128 KiB.
 constexpr int kChunkWords = 32768;
 // Per-edge mode: 112 KiB, leaving room for the run queue's four arrays.
 constexpr int kChunkWordsPE = 28672;
 constexpr int kC4HeavyBlock = 1024;
-constexpr int kHeavyGroup = 2048;
 // Heavy items (global mode) of vertices with at most this many lower
-// neighbours take the walking path (each thread owns up to three lists,
-// cursors in registers); long runs are queued for whole waves, in a queue
-// with a slot per list.
+// neighbours keep every list's cursor in registers (up to three lists per
+// thread); long runs are queued for whole waves, in a queue with a slot per
+// list.  Vertices with more lists walk them in groups of two per thread,
+// cursors kept in global memory between groups.
 constexpr int kWalkLists = 3 * kC4HeavyBlock;
 constexpr int kWalkListsPE = 2 * kC4HeavyBlock;  // per-edge mode: two lists per thread
 // Target wedges per heavy work item.
@@ -182,11 +181,8 @@ struct C4Args {
   const int4 *items;  // (x, y_begin, y_end, -)
   const int64_t *nitems;
   u64 *queue;
-  int32_t *gcur;  // per slot: cursor per lower neighbour
-  int32_t *gbeg;  // per slot: end of each active list
-  int32_t *gnext; // per slot: next entry of each active list
-  int32_t *gsel;  // per slot: lists with entries in the chunk
-  int32_t *gvid;  // per slot (per-edge): list index of each active list
+  int32_t *gcur;  // per slot: cursor per lower neighbour (items of many lists)
+  int32_t *gbeg;  // per slot: end of each list
   int32_t *gcb;   // per slot (per-edge): run start of each list in the chunk
   int lmax;
   const int32_t *deg2;  // degree of each rank (non-decreasing)
