@@ -369,6 +369,79 @@ __device__ __forceinline__ int band_chunk(int c0, int yb, int nL, const int32_t 
   return (int)best;
 }
 
+// Per-edge credits of heavy wedges: wedge x - v - y adds c(x, y) - 1 to
+// edge (v, y) at v's entry b for y.  With C4h (every entry's credit total
+// fits 32 bits) the entries b, b + 1 (b even) share one 64-bit atomic add;
+// otherwise each entry takes its own, into C4w.
+__device__ __forceinline__ void credit_pair(const C4Args &g, int b, uint32_t lo, uint32_t hi) {
+  if (g.C4h) {
+    if (lo | hi)
+      atomicAdd(reinterpret_cast<unsigned long long *>(g.C4h + b),
+                (unsigned long long)(((u64)hi << 32) | lo));
+  } else {
+    if (lo) atomicAdd(&g.C4w[b], (u64)lo);
+    if (hi) atomicAdd(&g.C4w[b + 1], (u64)hi);
+  }
+}
+
+__device__ __forceinline__ void credit_one(const C4Args &g, int b, uint32_t v) {
+  if (!v) return;
+  if (g.C4h) atomicAdd(g.C4h + b, v);
+  else atomicAdd(&g.C4w[b], (u64)v);
+}
+
+// The chunk's counts are complete: credits of one thread's run [st, en) of a
+// list (entries below c0 take none), read PF at a time from an even entry;
+// returns their sum, which also goes to edge (x, v).
+template <int PF>
+__device__ __forceinline__ u64 credit_run_thread(const C4Args &g, const uint32_t *cnt, int lb, int c0,
+                                                 int st, int en) {
+  static_assert(PF % 2 == 0, "pairs");
+  u64 cr = 0;
+  for (int b = st & ~1; b < en; b += PF) {
+    int yv[PF];
+#pragma unroll
+    for (int k = 0; k < PF; k++) yv[k] = b + k >= st && b + k < en ? g.col2[b + k] : -1;
+    uint32_t cv[PF];
+#pragma unroll
+    for (int k = 0; k < PF; k++) {
+      cv[k] = yv[k] >= c0 ? band_get(cnt, lb, yv[k] - c0) - 1 : 0u;  // c >= 1: the wedge itself
+      cr += cv[k];
+    }
+#pragma unroll
+    for (int k = 0; k < PF; k += 2) credit_pair(g, b + k, cv[k], cv[k + 1]);
+  }
+  return cr;
+}
+
+// The same for a run read by a whole wave, 64 consecutive entries at a time;
+// an even entry's lane adds its odd neighbour's credit with its own.  Returns
+// the run's total on every lane.
+__device__ __forceinline__ u64 credit_run_wave(const C4Args &g, const uint32_t *cnt, int lb, int c0,
+                                               int st, int en) {
+  const int lane = lane_id();
+  u64 cr = 0;
+  for (int b0 = st; b0 < en; b0 += kWave) {  // the same trip count on every lane
+    const int b = b0 + lane;
+    uint32_t cv = 0;
+    if (b < en) {
+      const int y = g.col2[b];
+      if (y >= c0) cv = band_get(cnt, lb, y - c0) - 1;
+    }
+    cr += cv;
+    const uint32_t next = __shfl_down(cv, 1, kWave);  // zero past the run
+    if (b < en) {
+      if (!(b & 1)) {
+        if (lane < kWave - 1) credit_pair(g, b, cv, next);
+        else credit_one(g, b, cv);  // b + 1 is lane 0's of the next round
+      } else if (lane == 0) {
+        credit_one(g, b, cv);  // its even neighbour is not in this round
+      }
+    }
+  }
+  return wave_sum_u64(cr);
+}
+
 // One heavy item by walking: list i of the item (the part of N(v_i) below x)
 // is owned by thread i mod block, at most LPT per thread, with its cursor and
 // the next PF entries in registers (nL <= kWalkLists, kWalkListsPE in
@@ -547,36 +620,11 @@ __device__ __forceinline__ void heavy_walk_item(const C4Args &g, int Lx, int nL,
       // each wave the queued parts it read.
 #pragma unroll
       for (int r = 0; r < LPT; r++) {
-        u64 cr = 0;
-        for (int b = ps[r]; b < q[r]; b += PF) {
-          int yv[PF];
-#pragma unroll
-          for (int k = 0; k < PF; k++) yv[k] = b + k < q[r] ? g.col2[b + k] : -1;
-#pragma unroll
-          for (int k = 0; k < PF; k++) {
-            if (yv[k] < c0) continue;  // past the part, or below the first counted rank
-            const uint32_t c = band_get(cnt, lb, yv[k] - c0);
-            if (c >= 2) {
-              atomicAdd(&g.C4w[b + k], (u64)(c - 1));
-              cr += c - 1;
-            }
-          }
-        }
+        const u64 cr = credit_run_thread<PF>(g, cnt, lb, c0, ps[r], q[r]);
         if (cr) atomicAdd(&g.C4w[Lx + tid + r * kC4HeavyBlock], cr);
       }
       for (int qi = wave; qi < nq; qi += NW) {
-        const int st = qstart[qi], en = qpos[qi];
-        u64 cr = 0;
-        for (int b = st + lane; b < en; b += kWave) {
-          const int y = g.col2[b];
-          if (y < c0) continue;
-          const uint32_t c = band_get(cnt, lb, y - c0);
-          if (c >= 2) {
-            atomicAdd(&g.C4w[b], (u64)(c - 1));
-            cr += c - 1;
-          }
-        }
-        cr = wave_sum_u64(cr);
+        const u64 cr = credit_run_wave(g, cnt, lb, c0, qstart[qi], qpos[qi]);
         if (lane == 0 && cr) atomicAdd(&g.C4w[Lx + qid[qi]], cr);
       }
       __syncthreads();  // the counters are read before the sweep clears them
@@ -737,39 +785,14 @@ __device__ __forceinline__ void heavy_walk_groups(const C4Args &g, int Lx, int n
             qid[slot] = i;
             continue;
           }
-          u64 cr = 0;
-          for (int b = st; b < en; b += PF) {
-            int yv[PF];
-#pragma unroll
-            for (int k = 0; k < PF; k++) yv[k] = b + k < en ? g.col2[b + k] : -1;
-#pragma unroll
-            for (int k = 0; k < PF; k++) {
-              if (yv[k] < c0) continue;  // past the run, or below the first counted rank
-              const uint32_t c = band_get(cnt, lb, yv[k] - c0);
-              if (c >= 2) {
-                atomicAdd(&g.C4w[b + k], (u64)(c - 1));
-                cr += c - 1;
-              }
-            }
-          }
+          const u64 cr = credit_run_thread<PF>(g, cnt, lb, c0, st, en);
           if (cr) atomicAdd(&g.C4w[Lx + i], cr);
         }
         __syncthreads();
         const int nq = s_nq[par];
         if (tid == 0) s_nq[par ^ 1] = 0;
         for (int qi = wave; qi < nq; qi += NW) {
-          const int st = qstart[qi], en = qpos[qi];
-          u64 cr = 0;
-          for (int b = st + lane; b < en; b += kWave) {
-            const int y = g.col2[b];
-            if (y < c0) continue;
-            const uint32_t c = band_get(cnt, lb, y - c0);
-            if (c >= 2) {
-              atomicAdd(&g.C4w[b], (u64)(c - 1));
-              cr += c - 1;
-            }
-          }
-          cr = wave_sum_u64(cr);
+          const u64 cr = credit_run_wave(g, cnt, lb, c0, qstart[qi], qpos[qi]);
           if (lane == 0 && cr) atomicAdd(&g.C4w[Lx + qid[qi]], cr);
         }
         __syncthreads();  // the queue is rewritten by the next group
@@ -1022,19 +1045,24 @@ __global__ __launch_bounds__(256) void k_hub_long(HubArgs g) {
 // two directed entries; the lower one is folded into the upper position,
 // where the per-edge outputs are read.
 __global__ void k_c4_fold(const u64 *ekeys, const int32_t *col2, const int32_t *tpos, int64_t nnz,
-                          int B, u64 *C4w) {
+                          int B, u64 *C4w, const uint32_t *C4h) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nnz) return;
   const int32_t x = (int32_t)(ekeys[p] >> B);
-  if (col2[p] > x) C4w[p] += C4w[tpos[p]];
+  if (col2[p] > x) {
+    const int32_t q = tpos[p];
+    u64 s = C4w[q];
+    if (C4h) s += (u64)C4h[p] + C4h[q];
+    C4w[p] += s;
+  }
 }
 
 }  // namespace
 
 int launch_c4_fold(const u64 *ekeys, const int32_t *col2, const int32_t *tpos, int64_t nnz, int B,
-                   u64 *C4w, hipStream_t s) {
+                   u64 *C4w, const uint32_t *C4h, hipStream_t s) {
   if (nnz <= 0) return GC_OK;
-  k_c4_fold<<<grid1d(nnz, 256), 256, 0, s>>>(ekeys, col2, tpos, nnz, B, C4w);
+  k_c4_fold<<<grid1d(nnz, 256), 256, 0, s>>>(ekeys, col2, tpos, nnz, B, C4w, C4h);
   GC_TRY_HIP(hipGetLastError());
   return GC_OK;
 }

@@ -55,6 +55,7 @@ struct Fixed {
   PrepassArgs pp;
   uint32_t *T;
   u64 *K4w, *C4w, *Dw;
+  uint32_t *C4h;      // per-edge: heavy wedge credits, 32 bits per entry
   u64 *Bw, *tv, *sv;  // local vectors only
   int64_t *cu;
   u64 *partials;
@@ -93,9 +94,11 @@ void alloc_fixed(Arena &a, const Plan &P, Fixed &f) {
     f.K4w = a.take<u64>(nnz);
     f.C4w = a.take<u64>(nnz);
     f.Dw = a.take<u64>(nnz);
+    f.C4h = a.take<uint32_t>(nnz + 2);
     f.cu = a.take<int64_t>(n + 1);
   } else {
     f.K4w = f.C4w = f.Dw = nullptr;
+    f.C4h = nullptr;
     f.cu = nullptr;
   }
   if (P.local) {
@@ -192,15 +195,17 @@ DynNeed dyn_need(const Plan &P, const Counters &hc) {
   return d;
 }
 
-// Upper bound of dyn_need before the prepass (workspace size query).
-DynNeed dyn_bound(const Plan &P, int max_deg, int max_ucnt) {
+// Upper bound of dyn_need before the prepass (workspace size query);
+// wedge_bound bounds the wedges of all vertices (sum of deg(x) |U(x)|).
+DynNeed dyn_bound(const Plan &P, int max_deg, int max_ucnt, u64 wedge_bound) {
   DynNeed d;
   const bool global_tk = max_ucnt > kTkLim3 || (P.per_edge && max_ucnt > kTkLim2);
   d.kmax_global = global_tk ? max_ucnt : 0;
   d.nheavy = (int)P.n;
   d.lmax = max_deg;
   // sum of wedges <= sum_v d_v |U(v)| <= nnz * max |U|
-  d.items_cap = P.n + (int64_t)((u64)P.nnz * (u64)std::max(max_ucnt, 1) / kPieceWork) + 1;
+  const u64 wedges = std::min((u64)P.nnz * (u64)std::max(max_ucnt, 1), wedge_bound);
+  d.items_cap = P.n + (int64_t)(wedges / kPieceWork) + 1;
   d.slots = device_cus();
   return d;
 }
@@ -367,6 +372,7 @@ int run(const gc_csr *G, gc_u128 out17[17], int64_t *per_edge_out, int64_t *loca
     GC_TRY(fill<u64>(f.K4w, 0ull, nnz, s));
     GC_TRY(fill<u64>(f.C4w, 0ull, nnz, s));
     GC_TRY(fill<u64>(f.Dw, 0ull, nnz, s));
+    GC_TRY(fill<uint32_t>(f.C4h, 0u, nnz + 2, s));
     if (P.local) {
       GC_TRY(fill<u64>(f.Bw, 0ull, nnz, s));
       GC_TRY(fill<u64>(f.tv, 0ull, n, s));
@@ -531,9 +537,12 @@ int run(const gc_csr *G, gc_u128 out17[17], int64_t *per_edge_out, int64_t *loca
     c4.gbeg = dy.gbeg;
     c4.gcb = dy.gcb;
     c4.lmax = std::max(dn.lmax, 1);
+    // per-edge: 32-bit credits (two entries per atomic) when no sum can overflow
+    c4.C4h = hc.max_deg <= kC4hMaxDeg ? f.C4h : nullptr;
     GC_TRY(launch_cycles_heavy(c4, dn.slots, P.per_edge, s));
   }
-  if (P.per_edge) GC_TRY(launch_c4_fold(pp.esorted, pp.col2, pp.tpos, nnz, P.B, f.C4w, s));
+  if (P.per_edge)
+    GC_TRY(launch_c4_fold(pp.esorted, pp.col2, pp.tpos, nnz, P.B, f.C4w, c4.C4h, s));
   ev.record(6, s);
 
   // -- per-edge 4-cliques and D_e (needs final |Tri|)
@@ -712,7 +721,7 @@ size_t workspace_bound(int64_t n, int64_t nnz, int max_deg, int max_ucnt, bool p
   alloc_fixed(a, P, f);
   Arena b;
   Dyn d;
-  alloc_dyn(b, P, dyn_bound(P, max_deg, max_ucnt), d);
+  alloc_dyn(b, P, dyn_bound(P, max_deg, max_ucnt, ~0ull), d);
   return a.peak + b.peak + 1024;
 }
 
@@ -728,14 +737,15 @@ size_t workspace_size(const gc_csr *g, int per_edge, hipStream_t s, int *rc) {
   P.local = per_edge == 2;
   if (P.n == 0 || P.nnz == 0) return 256;
   int max_deg = 0, max_ucnt = 0;
-  *rc = probe_graph(g, s, &max_deg, &max_ucnt);
+  u64 wedge_bound = 0;
+  *rc = probe_graph(g, s, &max_deg, &max_ucnt, &wedge_bound);
   if (*rc) return 0;
   Arena a;
   Fixed f;
   alloc_fixed(a, P, f);
   Arena b;
   Dyn d;
-  alloc_dyn(b, P, dyn_bound(P, max_deg, max_ucnt), d);
+  alloc_dyn(b, P, dyn_bound(P, max_deg, max_ucnt, wedge_bound), d);
   return a.peak + b.peak + 1024;
 }
 

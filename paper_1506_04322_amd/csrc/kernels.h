@@ -120,8 +120,9 @@ struct PrepassArgs {
   u64 *esorted;    // set by the prepass: sorted (row << B | col) keys
 };
 
-// Maximum degree and maximum |U(x)| of a caller CSR (one sync on s).
-int probe_graph(const gc_csr *g, hipStream_t s, int *max_deg, int *max_ucnt);
+// Maximum degree, maximum |U(x)| and sum of deg(x) |U(x)| (a bound of the
+// wedges x - v - y with v, y below x) of a caller CSR (one sync on s).
+int probe_graph(const gc_csr *g, hipStream_t s, int *max_deg, int *max_ucnt, u64 *wedge_bound);
 int launch_validate(const int32_t *rp, const int32_t *col, int64_t n, int64_t nnz, int32_t *err,
                     hipStream_t s);
 int run_prepass(PrepassArgs &p, Arena &a, hipStream_t s);
@@ -187,7 +188,13 @@ struct C4Args {
   int lmax;
   const int32_t *deg2;  // degree of each rank (non-decreasing)
   int64_t n;
+  // Per-edge mode: the heavy wedges' credits per directed entry in 32 bits
+  // (nnz + 2 entries, folded into C4w), or null: into C4w.  Used when the
+  // maximum degree is at most kC4hMaxDeg: an entry (v, y) gains at most
+  // c(x, y) - 1 < deg(y) from each of the fewer than deg(v) vertices x.
+  uint32_t *C4h;
 };
+constexpr int kC4hMaxDeg = 65535;
 
 // Dense hub slabs (global mode).  The costliest heavy vertices are counted
 // kDenseSlab at a time: every vertex v gets a mask whose bit k says that v is
@@ -211,10 +218,10 @@ int launch_dense_slab(const HubArgs &g, hipStream_t s);
 
 int launch_cycles_light(C4Args g, bool per_edge, hipStream_t s);
 int launch_cycles_medium(C4Args g, bool per_edge, hipStream_t s);
-// Per-edge mode: adds each edge's lower directed entry of C4w into its upper
-// position.
+// Per-edge mode: adds each edge's lower directed entry of C4w, and both
+// entries of C4h (if not null), into its upper position of C4w.
 int launch_c4_fold(const u64 *ekeys, const int32_t *col2, const int32_t *tpos, int64_t nnz, int B,
-                   u64 *C4w, hipStream_t s);
+                   u64 *C4w, const uint32_t *C4h, hipStream_t s);
 int launch_cycles_heavy(C4Args g, int slots, bool per_edge, hipStream_t s);
 
 // ---------------------------------------------------------------- Step 3

@@ -7,6 +7,8 @@
 // its rank.  Under it, every vertex has at most sqrt(2m) upper neighbours,
 // which bounds the per-vertex state of the clique pass, and every 4-cycle has
 // one highest vertex, which the wedge pass aggregates on.
+#include <cstring>
+
 #include "kernels.h"
 #include "primitives.h"
 
@@ -342,11 +344,19 @@ __global__ void k_max_deg(const int32_t *rp, int64_t n, int32_t *out) {
   if (lane_id() == 0 && mx) atomicMax(out, mx);
 }
 
-// max over vertices of |U(x)|: neighbours later in the (degree, id) order.
-__global__ void k_max_ucnt(const int32_t *rp, const int32_t *col, int64_t n, int32_t *out) {
+// Max over vertices of |U(x)| (neighbours later in the (degree, id) order)
+// and sum over vertices of deg(x) |U(x)|, a bound of the wedges x - v - y
+// with v, y below x (each v in L(x) adds at most deg(v) of them).  One wave
+// per vertex, one atomic per block.
+__global__ __launch_bounds__(256) void k_max_ucnt(const int32_t *rp, const int32_t *col, int64_t n,
+                                                  int32_t *out, u64 *wsum) {
+  __shared__ int32_t smx[256 / kWave];
+  __shared__ u64 ssum[256 / kWave];
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
   const int lane = lane_id();
+  int mx = 0;
+  u64 sum = 0;
   for (int64_t u = wave; u < n; u += nwaves) {
     const int a = rp[u], b = rp[u + 1], du = b - a;
     int c = 0;
@@ -357,26 +367,42 @@ __global__ void k_max_ucnt(const int32_t *rp, const int32_t *col, int64_t n, int
       c += (dw > du || (dw == du && w > u)) ? 1 : 0;
     }
     for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, kWave);
-    if (lane == 0 && c) atomicMax(out, c);
+    mx = max(mx, c);
+    sum += (u64)c * (u64)du;
+  }
+  if (lane == 0) {
+    smx[threadIdx.x / kWave] = mx;
+    ssum[threadIdx.x / kWave] = sum;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 256 / kWave; w++) {
+      mx = max(mx, smx[w]);
+      sum += ssum[w];
+    }
+    if (mx) atomicMax(out, mx);
+    if (sum) atomicAdd(wsum, sum);
   }
 }
 
 }  // namespace
 
-int probe_graph(const gc_csr *g, hipStream_t s, int *max_deg, int *max_ucnt) {
+int probe_graph(const gc_csr *g, hipStream_t s, int *max_deg, int *max_ucnt, u64 *wedge_bound) {
   *max_deg = 0;
   *max_ucnt = 0;
+  *wedge_bound = 0;
   if (g->n == 0 || g->nnz == 0) return GC_OK;
   int32_t *d = nullptr;
-  GC_TRY_HIP(hipMallocAsync((void **)&d, 8, s));
-  int32_t h[2] = {0, 0};
-  hipError_t e = hipMemcpyAsync(d, h, 8, hipMemcpyHostToDevice, s);
+  GC_TRY_HIP(hipMallocAsync((void **)&d, 16, s));
+  int32_t h[4] = {0, 0, 0, 0};
+  hipError_t e = hipMemcpyAsync(d, h, 16, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) {
     k_max_deg<<<grid1d(g->n, 256), 256, 0, s>>>(g->row_ptr, g->n, d);
-    k_max_ucnt<<<grid1d(g->n * kWave, 256, 65536), 256, 0, s>>>(g->row_ptr, g->col, g->n, d + 1);
+    k_max_ucnt<<<grid1d(g->n * kWave, 256, 2048), 256, 0, s>>>(g->row_ptr, g->col, g->n, d + 1,
+                                                               reinterpret_cast<u64 *>(d + 2));
     e = hipGetLastError();
   }
-  if (e == hipSuccess) e = hipMemcpyAsync(h, d, 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(h, d, 16, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   const hipError_t f = hipFreeAsync(d, s);
   if (e == hipSuccess) e = f;
@@ -386,6 +412,9 @@ int probe_graph(const gc_csr *g, hipStream_t s, int *max_deg, int *max_ucnt) {
   }
   *max_deg = h[0];
   *max_ucnt = h[1];
+  u64 w;
+  std::memcpy(&w, h + 2, 8);
+  *wedge_bound = w;
   return GC_OK;
 }
 

@@ -317,8 +317,8 @@ def test_heavy_items_long_runs(nv):
     # below x in the degree order (ties by id): every list of x's heavy item
     # has a run of 30 in one chunk, longer than a thread's buffer, so all nv
     # lists go to the long-run queue together (one, two or three lists per
-    # thread up to 3072 lists; the general path above); the y's are heavy too, with
-    # runs of every length up to 29
+    # thread up to 3072 lists, groups of 2048 lists above); the y's are heavy
+    # too, with runs of every length up to 29
     ny = 30
     x = ny + nv
     edges = [(y, ny + i) for i in range(nv) for y in range(ny)] + [(ny + i, x) for i in range(nv)]
@@ -343,6 +343,56 @@ def test_heavy_items_long_runs(nv):
     rng = np.random.default_rng(nv)
     idx = np.unique(np.concatenate([rng.integers(0, len(eu), 120),
                                     np.nonzero(ev == x)[0][:40], np.nonzero(eu < ny)[0][:40]]))
+    T, K4, C4 = oracle.per_edge(g, eu[idx], ev[idx])
+    np.testing.assert_array_equal(pe[0][idx], T)
+    np.testing.assert_array_equal(pe[1][idx], K4)
+    np.testing.assert_array_equal(pe[2][idx], C4)
+
+
+def hub_lists_graph(nv, ny=30):
+    x = ny + nv
+    edges = [(y, ny + i) for i in range(nv) for y in range(ny)] + [(ny + i, x) for i in range(nv)]
+    return graphgen.from_edges(x + 1, edges)
+
+
+@pytest.mark.parametrize("case", ["rmat14", "hub_lists_3000", "chung_lu_small"])
+def test_per_edge_heavy_credits_packed_and_wide(case):
+    # Heavy wedge credits go to 32-bit totals per entry, two neighbouring
+    # entries per atomic add, unless the maximum degree exceeds 65535 (then
+    # each entry takes its own 64-bit add).  A disjoint star with 65536 leaves
+    # switches the graph to the wide credits and changes none of the values
+    # of the original edges, which come first in canonical order.
+    if case == "rmat14":
+        g = graphgen.rmat(14, 16, 0.57, 0.19, 0.19, 5)
+    elif case == "hub_lists_3000":
+        g = hub_lists_graph(3000)
+    else:
+        g = graphgen.chung_lu(20000, 2.1, 13.0, 218000, 3)
+    want = oracle.identity_route(g)
+    gl.graphlet_timing_enable(True)
+    try:
+        got, pe = gpu_counts(g, per_edge=True, validate=False)
+        t = gl.graphlet_last_timing()
+    finally:
+        gl.graphlet_timing_enable(False)
+    assert got == want and t["wedges_heavy"] > 0
+    assert int(pe[0].sum()) == 3 * want[2] and int(pe[1].sum()) == 6 * want[6]
+    assert int(pe[2].sum()) == 4 * want[9]
+    eu, ev = oracle.edges(g)
+    leaves = 65536
+    star = np.stack([np.full(leaves, g.n), g.n + 1 + np.arange(leaves)], axis=1)
+    g2 = graphgen.from_edges(g.n + 1 + leaves, np.concatenate([np.stack([eu, ev], axis=1), star]))
+    got2, pe2 = gpu_counts(g2, per_edge=True, validate=False)
+    m = pe.shape[1]
+    np.testing.assert_array_equal(pe2[:, :m], pe)
+    assert not pe2[:, m:].any()  # a star closes no triangle or cycle
+    # sampled edges, the heaviest endpoints' among them, against the literal
+    # per-edge oracle
+    deg = np.diff(g.row_ptr)
+    rng = np.random.default_rng(7)
+    top = np.argsort(deg)[-3:]
+    idx = np.unique(np.concatenate([rng.integers(0, len(eu), 150)] +
+                                   [np.nonzero((eu == h) | (ev == h))[0][:30] for h in top]))
     T, K4, C4 = oracle.per_edge(g, eu[idx], ev[idx])
     np.testing.assert_array_equal(pe[0][idx], T)
     np.testing.assert_array_equal(pe[1][idx], K4)
