@@ -34,6 +34,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+# 32-bit integer vector lane operations per second: 256 compute units x 4
+# SIMDs x 16 lanes per clock x 2.4 GHz (the fp32 vector rate of 78.6 TFLOP/s
+# counts an FMA as two operations; integer AND / popcount are one each)
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def log(*a):
@@ -146,7 +150,8 @@ def cpu_baseline(g, name: str, seconds: float):
     return res
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_c4_heavy_bal_rmat22_traffic.md")
+TRAFFIC_PROFILES = {"rmat22": "k_c4_heavy_bal_rmat22_traffic.md",
+                    "cl": "k_c4_heavy_bal_chung_lu_per_edge_traffic.md"}
 TRAFFIC_SOURCES = ["paper_1506_04322_amd/csrc/cycles.hip", "paper_1506_04322_amd/csrc/kernels.h",
                    "paper_1506_04322_amd/csrc/common.h"]
 
@@ -155,10 +160,11 @@ def measured_traffic(kernel: str, workload: str, field: str = "traffic_bytes_per
     """HBM bytes per launch of `kernel` (or another recorded field, such as
     its L2 hit rate) from the committed rocprofv3 counters, or None when they
     were taken on other sources or another workload."""
-    if workload != "rmat22" or not os.path.exists(TRAFFIC_PROFILE):
+    path = os.path.join(ROOT, "profiles", TRAFFIC_PROFILES.get(workload, "-"))
+    if not os.path.exists(path):
         return None
     fields = {}
-    for line in open(TRAFFIC_PROFILE):
+    for line in open(path):
         if ":" in line and not line.startswith(("|", "#", "`")):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
@@ -286,6 +292,39 @@ def run_single(args, torch, gl):
     return res
 
 
+def batch_alu_work(b, triangles):
+    """Algorithmic work of the batched kernel over a batch, in 64-bit word
+    operations (AND of two adjacency-row words and a popcount): per graph,
+    W words per row times (edges [Step 1] + triangles [the 4-clique listing
+    from each triangle's lowest edge, at most W words each] + vertex pairs
+    of the 4-cycle pass [all pairs, or for a sparse graph the pairs two
+    steps apart, plus the row unions that find them]), with the kernel's own
+    dense / sparse choice (sum deg^2 + 2m < n^2 / 2 is sparse)."""
+    import numpy as np
+    import scipy.sparse as sp
+
+    no, rp, col = b.node_off, b.row_ptr, b.col
+    total = 0
+    for gi in range(b.graphs):
+        r0, r1 = int(no[gi]), int(no[gi + 1])
+        n = r1 - r0
+        e0, e1 = int(rp[r0]), int(rp[r1])
+        nnz = e1 - e0
+        w = (n + 63) // 64
+        deg = np.diff(rp[r0:r1 + 1]).astype(np.int64)
+        work = (nnz // 2 + int(triangles[gi])) * w
+        if int((deg * deg).sum()) + nnz < n * n // 2:
+            a = sp.csr_matrix((np.ones(nnz, np.int32), col[e0:e1], rp[r0:r1 + 1] - e0),
+                              shape=(n, n))
+            a2 = (a @ a).tocoo()
+            work += int((a2.col > a2.row).sum()) * w
+            work += int((deg * (w - ((np.arange(n) + 1) >> 6))).sum())
+        else:
+            work += n * (n - 1) // 2 * w
+        total += work
+    return total
+
+
 def plan_device_ms(torch, plan, reps=5):
     """Device time of one replay, from events on the replay's stream."""
     st = torch.cuda.current_stream()
@@ -337,6 +376,17 @@ def run_batch(args, torch, gl):
         raise SystemExit("batched plan replay differs from the one-shot call")
     ms_dev = plan_device_ms(torch, plan)
     plan.close()
+    # the kernel's roofline: 4 lane operations per word operation (two 32-bit
+    # ANDs, two 32-bit popcounts), over the device time of one replay
+    word_ops = batch_alu_work(b, out[:, 2].cpu().numpy())
+    achieved = 4 * word_ops / (ms_dev / 1e3) / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2),
+            "unit": "Tops/s (32-bit integer lane operations)",
+            "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None, "kernel": "k_batched",
+            "ops_per_launch": 4 * word_ops,
+            "work_unit": "64-bit row-word AND + popcount = 4 lane operations; one replay "
+                         "(every class launch) of the batch",
+            "lds_bytes_per_word_op": 16}
     matches = None
     st = stored_oracle("batch8192")
     if st is not None and st.get("sha256") == b.sha256():
@@ -386,7 +436,7 @@ def run_batch(args, torch, gl):
         "dtype": "int64 (exact integer)", "data": "synthetic",
         "config": {"workload": "batch8192", "graphs": b.graphs, "csr_sha256": b.sha256(),
                    "params": C.BATCH},
-        "plan": info, "tune_s": tune_s, "device_ms_per_step": ms_dev,
+        "plan": info, "tune_s": tune_s, "device_ms_per_step": ms_dev, "roofline": roof,
         "one_shot_graphs_per_s": b.graphs / (oneshot_ms / 1e3),
         "per_graph_launches": {"graphs_per_s": 1.0 / per_graph_s,
                                "sample": f"{len(dev_graphs)} graphs of the batch, one "
@@ -754,7 +804,7 @@ def main():
             res["batched"] = {k: b[k] for k in (
                 "metric", "value", "unit", "ms_per_step", "device_ms_per_step",
                 "one_shot_graphs_per_s", "per_graph_launches", "speedup_vs_per_graph",
-                "matches_oracle", "plan", "cpu_baseline")}
+                "matches_oracle", "plan", "cpu_baseline", "roofline")}
             res["batched"]["config"] = b["config"]
             sv = run_serve(args, torch, gl)
             res["serve"] = {k: sv[k] for k in (
