@@ -16,11 +16,10 @@
 // row i), packed triangularly; a column counter per local vertex gives the
 // lower half's contribution to |Tri|.  U(u) is indexed by an LDS hash, with
 // a bit filter in front of it: most candidates are not in U(u), and one LDS
-// read turns them away (the kernels are bound by instruction issue, not by
-// the gathers).  Per-edge mode keeps symmetric rows, so that every local
-// edge can read its common-neighbour count (4-cliques through that edge);
-// rows of up to 896 local vertices stay in LDS, larger ones (up to 1088)
-// use a per-workgroup slot in global memory.
+// read turns them away before the probe.  Per-edge mode keeps symmetric
+// rows, so that every local edge can read its common-neighbour count
+// (4-cliques through that edge); rows of up to 896 local vertices stay in
+// LDS, larger ones (up to 1088) use a per-workgroup slot in global memory.
 #include <algorithm>
 
 #include "kernels.h"
