@@ -337,15 +337,22 @@ __attribute__((amdgpu_waves_per_eu(BLOCK <= 512 ? 8 : 1))) void k_tk_up(TkArgs g
 //   |Tri(u,U_i)| + |Tri(u,U_j)| - 2 goes to D of the edge, and
 //   |Tri(u,U_j)| + |Tri(U_i,U_j)| - 2 to D of (u, U_i) (and symmetrically).
 // Vertices of the list with k <= KMIN (or k > KCAP) are left to another
-// launch over the same list.
-template <int BLOCK, int KCAP, int HS, bool GR, int KMIN = 0>
-__global__ __launch_bounds__(BLOCK) void k_tk_pe(TkArgs g) {
+// launch over the same list.  With HBITS > 0, pass 1 marks its hits in an LDS
+// bitmap over the candidate indices (when there are at most HBITS
+// candidates), and pass 2 walks the marked candidates only: about one
+// candidate in ten is a triangle.
+// The 64-thread shape is held to 64 VGPRs, and its bitmap to 480 bytes, so
+// that it runs 8 waves per SIMD.
+template <int BLOCK, int KCAP, int HS, bool GR, int KMIN = 0, int HBITS = 0>
+__global__ __launch_bounds__(BLOCK)
+__attribute__((amdgpu_waves_per_eu(BLOCK == 64 ? 8 : 1))) void k_tk_pe(TkArgs g) {
   constexpr int WC = (KCAP + 63) / 64;
   constexpr int RUN = 6;
   constexpr int FLOG = (31 - __builtin_clz(HS)) + (HS <= 1024 ? 3 : 2);  // as in k_tk_up
   constexpr int FW = (1 << FLOG) / 32;
+  constexpr int HBW = HBITS > 0 ? HBITS / 32 : 1;
   __shared__ int32_t U[KCAP], V[KCAP], P[KCAP + 1], rid[KCAP], H[HS], sums[BLOCK];
-  __shared__ uint32_t Tu[KCAP], A1[KCAP], F[FW];
+  __shared__ uint32_t Tu[KCAP], A1[KCAP], F[FW], HB[HBW];
   __shared__ u64 A2[KCAP], B2[KCAP];  // B2: degree sums for edges (u, U_i)
   __shared__ u64 Rl[GR ? 1 : KCAP * WC];
   __shared__ int nrows;
@@ -404,6 +411,12 @@ __global__ __launch_bounds__(BLOCK) void k_tk_pe(TkArgs g) {
     const int nr = nrows;
     block_scan_excl<BLOCK>(P, nr, sums);
     const int total = P[nr];
+    const bool hits = HBITS > 0 && total <= HBITS;  // the same on every thread
+    const int nhw = (total + 31) >> 5;
+    if (hits) {
+      for (int w = tid; w < nhw; w += BLOCK) HB[w] = 0;
+      __syncthreads();
+    }
     // Candidates past the bit filter are packed per wave (as candidate
     // indices, in the scan's scratch) and probed 64 at a time, as in k_tk_up.
     int32_t *qt = sums + (tid / kWave) * kWave;
@@ -423,6 +436,7 @@ __global__ __launch_bounds__(BLOCK) void k_tk_pe(TkArgs g) {
           if (j >= 0 && pass == 0) {
             atomicOr(&R[(size_t)ir * W + (j >> 6)], 1ull << (j & 63));
             atomicOr(&R[(size_t)j * W + (ir >> 6)], 1ull << (ir & 63));
+            if (hits) atomicOr(&HB[t >> 5], 1u << (t & 31));
           } else if (j >= 0) {
             const u64 *Ri = R + (size_t)ir * W, *Rj = R + (size_t)j * W;
             uint32_t c = 0;
@@ -447,24 +461,47 @@ __global__ __launch_bounds__(BLOCK) void k_tk_pe(TkArgs g) {
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       };
-      int cursor = 0;  // row at or before the wave's next slab
-      for (int s0 = (tid / kWave) * kWave * RUN; s0 < total; s0 += BLOCK * RUN) {
-        int pos[RUN], row[RUN], xv[RUN];
-        slab_positions<RUN>(P, V, rid, nr, total, s0, cursor, pos, row);
-#pragma unroll
-        for (int r = 0; r < RUN; r++) xv[r] = g.col2[pos[r] >= 0 ? pos[r] : 0];
-#pragma unroll
-        for (int r = 0; r < RUN; r++) {
-          const uint32_t f = fslot<FLOG>(xv[r]);
-          const bool ok = pos[r] >= 0 && ((F[f >> 5] >> (f & 31)) & 1u);
-          const u64 b = __ballot(ok);
-          const int cnt = __popcll(b);
-          if (qn + cnt > kWave) {  // the same on every lane
-            probe(qn);
-            qn = 0;
+      if (pass == 1 && hits) {
+        // the marked candidates: each lane takes one word of the bitmap and
+        // hands out one of its bits per round (hits are sparse here, so the
+        // queue's entries, spread over 64 words, rarely share lines anyway)
+        for (int w0 = (tid / kWave) * kWave; w0 < nhw; w0 += BLOCK) {
+          const int w = w0 + lane_id();
+          uint32_t bits = w < nhw ? HB[w] : 0u;
+          while (__ballot(bits != 0)) {  // the same on every lane
+            const bool ok = bits != 0;
+            const int t = (w << 5) + (ok ? __ffs(bits) - 1 : 0);
+            bits &= bits - 1;
+            const u64 b = __ballot(ok);
+            const int cnt = __popcll(b);
+            if (qn + cnt > kWave) {
+              probe(qn);
+              qn = 0;
+            }
+            if (ok) qt[qn + __popcll(b & lanemask_lt())] = t;
+            qn += cnt;
           }
-          if (ok) qt[qn + __popcll(b & lanemask_lt())] = s0 + r * kWave + lane_id();
-          qn += cnt;
+        }
+      } else {
+        int cursor = 0;  // row at or before the wave's next slab
+        for (int s0 = (tid / kWave) * kWave * RUN; s0 < total; s0 += BLOCK * RUN) {
+          int pos[RUN], row[RUN], xv[RUN];
+          slab_positions<RUN>(P, V, rid, nr, total, s0, cursor, pos, row);
+#pragma unroll
+          for (int r = 0; r < RUN; r++) xv[r] = g.col2[pos[r] >= 0 ? pos[r] : 0];
+#pragma unroll
+          for (int r = 0; r < RUN; r++) {
+            const uint32_t f = fslot<FLOG>(xv[r]);
+            const bool ok = pos[r] >= 0 && ((F[f >> 5] >> (f & 31)) & 1u);
+            const u64 b = __ballot(ok);
+            const int cnt = __popcll(b);
+            if (qn + cnt > kWave) {  // the same on every lane
+              probe(qn);
+              qn = 0;
+            }
+            if (ok) qt[qn + __popcll(b & lanemask_lt())] = s0 + r * kWave + lane_id();
+            qn += cnt;
+          }
         }
       }
       if (qn > 0) probe(qn);
@@ -612,7 +649,11 @@ int launch_cliques(TkArgs g, int bin, bool per_edge, hipStream_t s) {
     }
   } else {
     switch (bin) {
-      case 0: k_tk_pe<64, kTkLim0, 256, false><<<grid(65536), 64, 0, s>>>(g); break;
+      // the smallest class keeps a hit bitmap of 3840 candidates (three
+      // quarters of its candidates on the Chung-Lu graph, one in ten a
+      // triangle); for the larger classes the second pass is dominated by
+      // the probes and their atomics, and a bitmap measured no gain
+      case 0: k_tk_pe<64, kTkLim0, 256, false, 0, 3840><<<grid(65536), 64, 0, s>>>(g); break;
       case 1: k_tk_pe<256, kTkLim1, 1024, false><<<grid(16384), 256, 0, s>>>(g); break;
       case 2: k_tk_pe<512, kTkLim2, 2048, false><<<grid(8192), 512, 0, s>>>(g); break;
       // symmetric rows of up to 896 vertices (98 KB) fit beside the lists;
