@@ -164,7 +164,7 @@ void alloc_dyn(Arena &a, const Plan &P, const DynNeed &d, Dyn &y) {
     measure_heavy_items(d.nheavy, a);
     if (P.per_edge) {  // scan of the canonical edge offsets
       const size_t m0 = a.mark();
-      (void)scan_exclusive<int64_t>(nullptr, nullptr, P.n, a, nullptr);
+      (void)scan_exclusive<int64_t>(nullptr, nullptr, P.n + 1, a, nullptr);
       a.release(m0);
     }
   }
@@ -571,7 +571,7 @@ int run(const gc_csr *G, gc_u128 out17[17], int64_t *per_edge_out, int64_t *loca
   s3.acc = pp.acc;
   if (P.per_edge) {
     GC_TRY(launch_orig_upper(G->row_ptr, G->col, n, f.cu, s));
-    GC_TRY(scan_exclusive<int64_t>(f.cu, f.cu, n, da, s));
+    GC_TRY(scan_exclusive<int64_t>(f.cu, f.cu, n + 1, da, s));
     s3.order = pp.order;
     s3.rp = G->row_ptr;
     s3.col = G->col;

@@ -99,13 +99,15 @@ __global__ __launch_bounds__(256) void k_step3(S3Args g) {
       const u64 c4 = g.C4w[p] - g.Dw[p] + 2 * k4;  // non-negative; wraps cancel
       a[A_K4] += k4;
       a[A_C4] += c4;
-      // canonical id of the edge in the caller's numbering
+      // canonical id of the edge in the caller's numbering: lo's upper
+      // entries start at cu[lo], and its list ends with them (cu[lo + 1] -
+      // cu[lo] of them), so hi is found among those alone
       const int32_t ua = g.order[x], ub = g.order[y];
       const int32_t lo = ua < ub ? ua : ub, hi = ua < ub ? ub : ua;
-      const int32_t r0 = g.rp[lo], r1 = g.rp[lo + 1];
-      const int split = lower_bound_dev<int32_t>(g.col + r0, r1 - r0, lo);
-      const int pos = lower_bound_dev<int32_t>(g.col + r0, r1 - r0, hi);
-      const int64_t id = g.cu[lo] + (pos - split);
+      const int64_t c0 = g.cu[lo];
+      const int nup = (int)(g.cu[lo + 1] - c0);
+      const int32_t r1 = g.rp[lo + 1];
+      const int64_t id = c0 + lower_bound_dev<int32_t>(g.col + (r1 - nup), nup, hi);
       if (g.out) {
         g.out[id] = (int64_t)T;
         g.out[g.m + id] = (int64_t)k4;
@@ -162,9 +164,15 @@ __global__ __launch_bounds__(256) void k_vertex_sums(const int32_t *rp2, const i
 }
 
 // Upper-neighbour counts in the caller's ids (canonical edge numbering).
+// up[u] = neighbours of u above u in the caller's numbering; up[n] = 0 (the
+// exclusive scan then ends with the edge count).
 __global__ void k_orig_upper(const int32_t *rp, const int32_t *col, int64_t n, int64_t *up) {
   const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= n) return;
+  if (u > n) return;
+  if (u == n) {
+    up[n] = 0;
+    return;
+  }
   const int a = rp[u], d = rp[u + 1] - a;
   up[u] = d - lower_bound_dev<int32_t>(col + a, d, (int32_t)u);
 }
@@ -192,7 +200,7 @@ int launch_vertex_sums(const int32_t *rp2, const int32_t *col2, const int32_t *l
 
 int launch_orig_upper(const int32_t *rp, const int32_t *col, int64_t n, int64_t *up,
                       hipStream_t s) {
-  k_orig_upper<<<grid1d(n, 256), 256, 0, s>>>(rp, col, n, up);
+  k_orig_upper<<<grid1d(n + 1, 256), 256, 0, s>>>(rp, col, n, up);
   GC_TRY_HIP(hipGetLastError());
   return GC_OK;
 }
