@@ -72,27 +72,57 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_hist(const u64 *keys, int64_t n
   hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
-// Stable scatter: keys of a tile keep their order within a digit.  Rounds
-// of 256 keys go in index order; inside a round, a key's rank among equal
-// digits is (keys of earlier rounds) + (keys of lower waves) + (lower lanes
-// of its own wave, found with eight ballots).
+// Stable scatter: keys of a tile keep their order within a digit.  The tile
+// is first put in digit order in LDS: a key's place is the tile's start of
+// its digit, plus the keys of that digit in earlier rounds of 256 (a running
+// count), in lower waves and in lower lanes of its own wave (eight ballots).
+// Then the tile is written out in that order, so that consecutive threads
+// write consecutive addresses within each digit's run.
 __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const u64 *in, u64 *out, int64_t n,
                                                          int shift, const uint32_t *offs,
                                                          int64_t ntiles) {
-  __shared__ uint32_t run[256];
+  __shared__ u64 stage[kRsTile];
+  __shared__ uint32_t run[256], lstart[256], goff[256];
   __shared__ uint32_t wcnt[kRsBlock / kWave][256];
   const int tid = threadIdx.x, wave = tid / kWave;
-  run[tid] = offs[(int64_t)tid * ntiles + blockIdx.x];
   const int64_t base = (int64_t)blockIdx.x * kRsTile;
+  const int cnt = (int)(n - base < kRsTile ? n - base : kRsTile);
+  goff[tid] = offs[(int64_t)tid * ntiles + blockIdx.x];
+  run[tid] = 0;
+  __syncthreads();
+  u64 key[kRsIpt];
+#pragma unroll
+  for (int r = 0; r < kRsIpt; r++) {
+    const int i = r * kRsBlock + tid;
+    key[r] = i < cnt ? in[base + i] : 0ull;
+    if (i < cnt) atomicAdd(&run[(uint32_t)(key[r] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  // the tile's start of each digit: an exclusive scan of its counts
+  {
+    const uint32_t c = run[tid];
+    uint32_t incl = c;
+    for (int off = 1; off < kWave; off <<= 1) {
+      const uint32_t t = __shfl_up(incl, off, kWave);
+      if (lane_id() >= off) incl += t;
+    }
+    if (lane_id() == kWave - 1) wcnt[0][wave] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int w = 0; w < wave; w++) before += wcnt[0][w];
+    lstart[tid] = before + incl - c;
+    run[tid] = before + incl - c;  // running place of the next key of each digit
+    __syncthreads();
+  }
   const u64 lt = lanemask_lt();
+#pragma unroll
   for (int r = 0; r < kRsIpt; r++) {
 #pragma unroll
     for (int w = 0; w < kRsBlock / kWave; w++) wcnt[w][tid] = 0;
     __syncthreads();
-    const int64_t i = base + (int64_t)r * kRsBlock + tid;
-    const bool valid = i < n;
-    const u64 key = valid ? in[i] : 0ull;
-    const uint32_t d = (uint32_t)(key >> shift) & 255u;
+    const int i = r * kRsBlock + tid;
+    const bool valid = i < cnt;
+    const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
     u64 peers = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; b++) {
@@ -107,15 +137,20 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const u64 *in, u64 *out
       uint32_t acc = run[tid];
 #pragma unroll
       for (int w = 0; w < kRsBlock / kWave; w++) {
-        uint32_t c = wcnt[w][tid];
+        const uint32_t c = wcnt[w][tid];
         wcnt[w][tid] = acc;
         acc += c;
       }
       run[tid] = acc;
     }
     __syncthreads();
-    if (valid) out[wcnt[wave][d] + lrank] = key;
-    __syncthreads();
+    if (valid) stage[wcnt[wave][d] + lrank] = key[r];
+    __syncthreads();  // wcnt is cleared by the next round
+  }
+  for (int i = tid; i < cnt; i += kRsBlock) {
+    const u64 k = stage[i];
+    const uint32_t d = (uint32_t)(k >> shift) & 255u;
+    out[goff[d] + (i - lstart[d])] = k;
   }
 }
 
