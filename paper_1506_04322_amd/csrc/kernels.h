@@ -205,7 +205,7 @@ constexpr int kDenseWords = kDenseSlab / 64;  // mask words per vertex
 constexpr int kDenseHubMax = 8192;     // candidates examined by the host
 constexpr int kDenseShortDeg = 1023;   // rows up to this degree: one thread, 10 bit planes
 constexpr double kDenseSlabPs = 2.9e9;      // measured cost of one slab pass (R-MAT s22)
-constexpr double kSparseWedgePs = 4.9;      // measured cost of one heavy wedge by work items
+constexpr double kSparseWedgePs = 2.84;     // measured cost of one heavy wedge by work items
 struct HubArgs {
   const int32_t *rp2, *col2, *lcnt;
   int64_t n;

@@ -9,10 +9,14 @@ constexpr int kScanBlock = 256;
 constexpr int kScanIpt = 8;
 constexpr int kScanTile = kScanBlock * kScanIpt;
 
+// A tile of kScanTile elements, kScanIpt consecutive ones per thread: the
+// thread totals are scanned within each wave by shuffles, the wave totals
+// through LDS after one barrier.
 template <class T>
 __global__ __launch_bounds__(kScanBlock) void k_scan_tile(const T *in, T *out, T *sums, int64_t n) {
-  __shared__ T s[kScanBlock];
+  __shared__ T wsum[kScanBlock / kWave];
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanIpt;
+  const int lane = lane_id(), wave = threadIdx.x / kWave;
   T v[kScanIpt];
   T tot = 0;
 #pragma unroll
@@ -21,16 +25,22 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tile(const T *in, T *out, T
     v[k] = i < n ? in[i] : T(0);
     tot += v[k];
   }
-  s[threadIdx.x] = tot;
-  __syncthreads();
-  for (int off = 1; off < kScanBlock; off <<= 1) {
-    T t = threadIdx.x >= (unsigned)off ? s[threadIdx.x - off] : T(0);
-    __syncthreads();
-    s[threadIdx.x] += t;
-    __syncthreads();
+  T incl = tot;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const T t = __shfl_up(incl, off, kWave);
+    if (lane >= off) incl += t;
   }
-  T run = s[threadIdx.x] - tot;
-  if (threadIdx.x == kScanBlock - 1 && sums) sums[blockIdx.x] = s[kScanBlock - 1];
+  if (lane == kWave - 1) wsum[wave] = incl;
+  __syncthreads();
+  T before = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < kScanBlock / kWave; w++) {
+    if (w < wave) before += wsum[w];
+    all += wsum[w];
+  }
+  T run = before + incl - tot;
+  if (threadIdx.x == kScanBlock - 1 && sums) sums[blockIdx.x] = all;
 #pragma unroll
   for (int k = 0; k < kScanIpt; k++) {
     int64_t i = base + k;
