@@ -99,6 +99,15 @@ typedef struct gc_u128 {
 size_t graphlet_workspace_size(const gc_csr *g, int per_edge, void *stream);
 
 /*
+ * A workspace size that suffices for every graph with these sizes, from n and
+ * nnz alone (per_edge as above): no device work and no stream.  It is
+ * larger than graphlet_workspace_size's figure for the same graph, which
+ * also reads the degrees.  Returns 0 on invalid sizes (negative, odd nnz, n
+ * or nnz of 2^31 - 1 or more, per_edge outside 0..2).
+ */
+size_t graphlet_workspace_bound(int64_t n, int64_t nnz, int per_edge);
+
+/*
  * Global counts, and optionally per-edge quantities, of one graph.
  *   g             the graph (device arrays, see gc_csr)
  *   out_counts    HOST gc_u128[17], the 17 counts in the order above

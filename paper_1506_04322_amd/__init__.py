@@ -60,6 +60,7 @@ _lib = None
 # Every symbol include/graphlet.h declares.
 EXPORTS = [
     "graphlet_workspace_size",
+    "graphlet_workspace_bound",
     "graphlet_count",
     "graphlet_count_local",
     "graphlet_count_vertex",
@@ -132,6 +133,8 @@ def load():
     P = ctypes.c_void_p
     lib.graphlet_workspace_size.argtypes = [ctypes.POINTER(_Csr), ctypes.c_int, P]
     lib.graphlet_workspace_size.restype = ctypes.c_size_t
+    lib.graphlet_workspace_bound.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int]
+    lib.graphlet_workspace_bound.restype = ctypes.c_size_t
     lib.graphlet_count.argtypes = [ctypes.POINTER(_Csr), ctypes.POINTER(_U128), P, P,
                                    ctypes.c_size_t, P, ctypes.c_uint32]
     lib.graphlet_count.restype = ctypes.c_int
@@ -241,6 +244,15 @@ def graphlet_workspace_size(row_ptr, col, n: int, per_edge=False, stream=None) -
     if size == 0:
         raise GraphletError(-1, graphlet_last_error())
     return int(size)
+
+
+def graphlet_workspace_bound(n: int, nnz: int, per_edge=False) -> int:
+    """Workspace bytes that suffice for any graph of n vertices and nnz
+    adjacency entries (host arithmetic only; per_edge: False/True or 0/1/2)."""
+    size = load().graphlet_workspace_bound(int(n), int(nnz), int(per_edge))
+    if size == 0:
+        raise GraphletError(-1, graphlet_last_error())
+    return size
 
 
 def graphlet_count(row_ptr, col, n: int, per_edge: bool = False, workspace=None,

@@ -14,6 +14,7 @@
 // keep it in global memory, heavy work items).  graphlet_workspace_size
 // bounds both from two cheap device reductions.
 #include <algorithm>
+#include <cmath>
 #include <functional>
 #include <cstring>
 #include <string>
@@ -725,6 +726,34 @@ size_t workspace_bound(int64_t n, int64_t nnz, int max_deg, int max_ucnt, bool p
   return a.peak + b.peak + 1024;
 }
 
+// From n and nnz alone: the maximum degree is at most min(n - 1, nnz), and
+// a vertex's k upper neighbours each have degree at least k, so k^2 <= nnz.
+size_t workspace_bound_host(int64_t n, int64_t nnz, int per_edge, int *rc) {
+  *rc = GC_OK;
+  if (n < 0 || nnz < 0 || n > 2147483646LL || nnz > 2147483646LL || (nnz & 1) || per_edge < 0 ||
+      per_edge > 2) {
+    set_error("invalid sizes n=%lld nnz=%lld per_edge=%d", (long long)n, (long long)nnz, per_edge);
+    *rc = GC_EINVAL;
+    return 0;
+  }
+  if (n == 0 || nnz == 0) return 256;
+  const int max_deg = (int)std::min<int64_t>(n - 1, nnz);
+  int64_t k = (int64_t)std::sqrt((double)nnz);
+  while (k * k > nnz) k--;
+  while ((k + 1) * (k + 1) <= nnz) k++;
+  const int max_ucnt = (int)std::min<int64_t>(k, max_deg);
+  gc_csr g{n, nnz, nullptr, nullptr};
+  Plan P = plan_of(&g, per_edge != 0);
+  P.local = per_edge == 2;
+  Arena a;
+  Fixed f;
+  alloc_fixed(a, P, f);
+  Arena b;
+  Dyn d;
+  alloc_dyn(b, P, dyn_bound(P, max_deg, max_ucnt, ~0ull), d);
+  return a.peak + b.peak + 1024;
+}
+
 size_t workspace_size(const gc_csr *g, int per_edge, hipStream_t s, int *rc) {
   *rc = check_args(g);
   if (*rc) return 0;
@@ -803,6 +832,17 @@ size_t graphlet_workspace_size(const gc_csr *g, int per_edge, void *stream) {
   int rc = 0;
   try {
     return gc::workspace_size(g, per_edge, (hipStream_t)stream, &rc);
+  } catch (...) {
+    gc::set_error("unexpected exception");
+    return 0;
+  }
+}
+
+size_t graphlet_workspace_bound(int64_t n, int64_t nnz, int per_edge) {
+  gc::clear_error();
+  int rc = 0;
+  try {
+    return gc::workspace_bound_host(n, nnz, per_edge, &rc);
   } catch (...) {
     gc::set_error("unexpected exception");
     return 0;

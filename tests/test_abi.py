@@ -74,6 +74,23 @@ def test_noalloc_batched_refuses_oversized_batches_before_any_device_work():
     assert "allocation-free limit" in gl.graphlet_last_error()
 
 
+def test_host_only_workspace_bound():
+    # sizes alone: no device work, so it runs without a GPU
+    if not os.path.exists(gl.LIB_PATH):
+        pytest.skip("library not built")
+    lib = gl.load()
+    assert lib.graphlet_workspace_bound(0, 0, 0) == 256
+    b0 = gl.graphlet_workspace_bound(1000, 16000, 0)
+    b1 = gl.graphlet_workspace_bound(1000, 16000, 1)
+    b2 = gl.graphlet_workspace_bound(1000, 16000, 2)
+    assert 0 < b0 < b1 < b2
+    assert gl.graphlet_workspace_bound(2000, 16000, 0) > b0
+    assert gl.graphlet_workspace_bound(1000, 32000, 0) > b0
+    for n, nnz, pe in ((1000, 15999, 0), (-1, 10, 0), (10, -2, 0), (10, 10, 3), (2**31, 10, 0)):
+        assert lib.graphlet_workspace_bound(n, nnz, pe) == 0, (n, nnz, pe)
+        assert "invalid" in gl.graphlet_last_error()
+
+
 def test_binding_fails_loudly_when_library_is_missing(tmp_path, monkeypatch):
     monkeypatch.setattr(gl, "LIB_PATH", str(tmp_path / "missing.so"))
     monkeypatch.setattr(gl, "_lib", None)

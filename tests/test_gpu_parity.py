@@ -712,6 +712,28 @@ def test_explicit_workspace():
     assert e.value.code == -6
 
 
+@pytest.mark.parametrize("per_edge", [0, 1, 2])
+def test_host_only_workspace_bound_suffices(per_edge):
+    # the bound from n and nnz alone covers the degree-aware size, and a
+    # workspace of exactly the bound runs every mode
+    import torch
+
+    for g in (graphgen.er_gnm(1000, 8000, 31), graphgen.rmat(12, 16, 0.57, 0.19, 0.19, 5),
+              hub_lists_graph(2500)):
+        rp, col = dev(g.row_ptr), dev(g.col)
+        bound = gl.graphlet_workspace_bound(g.n, len(g.col), per_edge)
+        assert bound >= gl.graphlet_workspace_size(rp, col, g.n, per_edge=per_edge)
+        ws = torch.empty(bound, dtype=torch.uint8, device="cuda:0")
+        want = oracle.identity_route(g)
+        if per_edge == 2:
+            c, _ = gl.graphlet_count_local(rp, col, g.n, workspace=ws)
+        elif per_edge == 1:
+            c, _ = gl.graphlet_count(rp, col, g.n, per_edge=True, workspace=ws)
+        else:
+            c = gl.graphlet_count(rp, col, g.n, workspace=ws)
+        assert c == want
+
+
 # ------------------------------------------------------------ batched
 
 
