@@ -82,7 +82,10 @@ template <int WORDS, int BLOCK>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 512 ? 4 : 5)))
 void k_batched(const int64_t *node_off, const int32_t *rp, const int32_t *col,
                const int32_t *list, int count, int64_t *out, int32_t *err) {
-  extern __shared__ u64 R[];  // n * WORDS
+  // row i at R + i * SW: an odd stride (in 64-bit words) spreads the rows
+  // that the lanes of a wave read at once over all LDS banks
+  constexpr int SW = WORDS | 1;
+  extern __shared__ u64 R[];  // n * SW
   __shared__ long long red[BLOCK / kWave][kBAcc];
   __shared__ unsigned long long s_sq;  // sum of squared degrees of the graph
   const int tid = threadIdx.x;
@@ -96,13 +99,13 @@ void k_batched(const int64_t *node_off, const int32_t *rp, const int32_t *col,
       continue;
     }
     const int64_t e0 = rp[r0];
-    for (int w = tid; w < n * WORDS; w += BLOCK) R[w] = 0;
+    for (int w = tid; w < n * SW; w += BLOCK) R[w] = 0;
     if (tid == 0) s_sq = 0;
     __syncthreads();
     // rows: each row written by one thread
     unsigned long long sq = 0;
     for (int i = tid; i < n; i += BLOCK) {
-      u64 *Ri = R + i * WORDS;
+      u64 *Ri = R + i * SW;
       const int64_t pa = rp[r0 + i], pb = rp[r0 + i + 1];
       for (int64_t p = pa; p < pb; p++) {
         const int j = col[p];
@@ -131,7 +134,7 @@ void k_batched(const int64_t *node_off, const int32_t *rp, const int32_t *col,
       }
       const int i = lo;
       if (j <= i) continue;
-      const u64 *Ri = R + i * WORDS, *Rj = R + j * WORDS;
+      const u64 *Ri = R + i * SW, *Rj = R + j * SW;
       long long T = 0;
       for (int w = 0; w < words; w++) T += __popcll(Ri[w] & Rj[w]);
       const long long du = rp[r0 + i + 1] - rp[r0 + i], dv = rp[r0 + j + 1] - rp[r0 + j];
@@ -155,7 +158,7 @@ void k_batched(const int64_t *node_off, const int32_t *rp, const int32_t *col,
         while (tri) {
           const int k = (w << 6) + __ffsll((long long)tri) - 1;
           tri &= tri - 1;
-          const u64 *Rk = R + k * WORDS;
+          const u64 *Rk = R + k * SW;
           for (int z = (k + 1) >> 6; z < words; z++) {
             u64 q = Ri[z] & Rj[z] & Rk[z];
             if (z == ((k + 1) >> 6)) q &= (~0ull) << ((k + 1) & 63);
@@ -172,17 +175,17 @@ void k_batched(const int64_t *node_off, const int32_t *rp, const int32_t *col,
     // sum_v deg(v)^2 row reads instead of n^2 / 2 (the same sum).
     if (s_sq + (unsigned long long)nnz < (unsigned long long)n * (unsigned long long)n / 2) {
       for (int a = tid; a < n; a += BLOCK) {
-        const u64 *Ra = R + a * WORDS;
+        const u64 *Ra = R + a * SW;
         const int64_t pa = rp[r0 + a], pb = rp[r0 + a + 1];
         const int wa = (a + 1) >> 6;
         for (int w = wa; w < words; w++) {  // a word of the union at a time
           u64 t = 0;
-          for (int64_t p = pa; p < pb; p++) t |= R[col[p] * WORDS + w];
+          for (int64_t p = pa; p < pb; p++) t |= R[col[p] * SW + w];
           if (w == wa) t &= (~0ull) << ((a + 1) & 63);
           while (t) {
             const int b = (w << 6) + __ffsll((long long)t) - 1;
             t &= t - 1;
-            const u64 *Rb = R + b * WORDS;
+            const u64 *Rb = R + b * SW;
             long long c = 0;
             for (int z = 0; z < words; z++) c += __popcll(Ra[z] & Rb[z]);
             A[B_C4NI] += ch2(c);
@@ -191,9 +194,9 @@ void k_batched(const int64_t *node_off, const int32_t *rp, const int32_t *col,
       }
     } else {
       for (int a = 0; a < n; a++) {
-        const u64 *Ra = R + a * WORDS;
+        const u64 *Ra = R + a * SW;
         for (int bb = a + 1 + tid; bb < n; bb += BLOCK) {
-          const u64 *Rb = R + bb * WORDS;
+          const u64 *Rb = R + bb * SW;
           long long c = 0;
           for (int w = 0; w < words; w++) c += __popcll(Ra[w] & Rb[w]);
           A[B_C4NI] += ch2(c);
@@ -454,7 +457,7 @@ bool layout(gc_batch_plan *p, const BatchShape &sh, std::vector<int32_t> *order)
     c.words = kWords[k];
     c.count = (int)bins[k].size();
     c.offset = (int)order->size();
-    c.lds = std::max<size_t>((size_t)nmax[k] * kWords[k] * sizeof(u64), 8);
+    c.lds = std::max<size_t>((size_t)nmax[k] * (kWords[k] | 1) * sizeof(u64), 8);  // odd row stride
     for (auto &x : bins[k]) order->push_back(x.second);
     L.push_back(c);
   }
