@@ -304,6 +304,7 @@ __attribute__((amdgpu_waves_per_eu(BLOCK <= 512 ? 8 : 1))) void k_tk_up(TkArgs g
 #pragma unroll
       for (int z = 0; z < WC; z++) c += (uint32_t)__popcll(ri[z]);
       if (c) atomicAdd(&g.T[base + i], c);
+      if (!g.k4) continue;  // per-edge mode: its own pass counts the 4-cliques
 #pragma unroll
       for (int w = 0; w < WC; w++) {
         u64 bits = ri[w];
@@ -321,7 +322,7 @@ __attribute__((amdgpu_waves_per_eu(BLOCK <= 512 ? 8 : 1))) void k_tk_up(TkArgs g
     __syncthreads();
   }
   const u128 s = block_sum_u128(k4acc, red);
-  if (threadIdx.x == 0 && s) atomic_add_u128(g.k4, s);
+  if (threadIdx.x == 0 && s && g.k4) atomic_add_u128(g.k4, s);
 }
 
 // ------------------------------------------------------------ per-edge mode

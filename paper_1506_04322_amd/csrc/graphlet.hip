@@ -473,7 +473,7 @@ int run(const gc_csr *G, gc_u128 out17[17], int64_t *per_edge_out, int64_t *loca
   tk.T = f.T;
   tk.K4w = f.K4w;
   tk.Dw = f.Dw;
-  tk.k4 = &pp.acc->k4;
+  tk.k4 = P.per_edge ? nullptr : &pp.acc->k4;  // per-edge: the K4 totals come from Step 3
   tk.k4x3 = &pp.acc->k4x3;
   tk.gR = dy.gR;
   tk.gI = dy.gI;

@@ -152,7 +152,7 @@ struct TkArgs {
   u64 *Dw;      // per-edge pass: D_e per upper position
   u64 *Bw;      // per-edge pass (local vectors): sum of deg(w) over w in Tri_e, or null
   const int32_t *deg2;  // degree by rank
-  u64 *k4;      // global mode: number of 4-cliques (128-bit)
+  u64 *k4;      // global mode: number of 4-cliques (128-bit); null in per-edge mode
   u64 *k4x3;    // fallback kernel: 3 x 4-cliques (128-bit)
   // global storage of the fallback kernel, per workgroup slot
   u64 *gR;
