@@ -432,7 +432,9 @@ int run_prepass(PrepassArgs &p, Arena &a, hipStream_t s) {
   k_degree_keys<<<grid1d(n, 256), 256, 0, s>>>(p.row_ptr, n, B, p.deg, p.rkeys, &p.cnt->max_deg);
   GC_TRY_HIP(hipGetLastError());
   u64 *rsorted;
-  GC_TRY(radix_sort_u64(p.rkeys, p.rkeys_alt, n, B + bits_for((u64)nnz), &rsorted, a, s));
+  // the keys are made in id order, so a stable sort on the degree bits alone
+  // orders them by (degree, id)
+  GC_TRY(radix_sort_u64(p.rkeys, p.rkeys_alt, n, bits_for((u64)nnz), &rsorted, a, s, B));
   k_rank<<<grid1d(n, 256), 256, 0, s>>>(rsorted, n, B, p.order, p.rank, p.deg2);
   GC_TRY_HIP(hipGetLastError());
   GC_TRY(scan_exclusive<int32_t>(p.deg2, p.rp2, n, a, s));
@@ -489,7 +491,9 @@ int sort_heavy(const PrepassArgs &p, int nh, u64 *keys, u64 *keys_alt, u64 **sor
   if (nh <= 0) return GC_OK;
   k_heavy_keys<<<grid1d(nh, 256), 256, 0, s>>>(p.c4h, nh, p.W, keys);
   GC_TRY_HIP(hipGetLastError());
-  GC_TRY(radix_sort_u64(keys, keys_alt, nh, 64, sorted, a, s));  // the key's high half is the order
+  // the key's high half is the order; the low half (the list index) is the
+  // input order, which a stable sort keeps for equal costs
+  GC_TRY(radix_sort_u64(keys, keys_alt, nh, 32, sorted, a, s, 32));
   return GC_OK;
 }
 
