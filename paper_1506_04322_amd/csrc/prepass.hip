@@ -159,49 +159,53 @@ __global__ void k_twin_keys(const int32_t *rp2, const int32_t *col2, const int32
   }
 }
 
+// Both twin positions of every pair, and the wedge counts: W[y] = wedges
+// y - v - w with v, w below y, the sum over v in L(y) of the length of the
+// prefix of N(v) below y, which ends at p (y's own position in N(v)).  The
+// keys are sorted by y, so each wave adds the lengths of a run of equal y
+// first (a segmented sum by shuffles) and its first lane adds them to W[y]
+// (zero on entry).
 __global__ void k_twin_pairs(const u64 *sorted, int64_t nup, const int32_t *rp2,
                              const int32_t *col2, const int32_t *lcnt, const int32_t *loff,
                              int64_t n, int64_t nnz, const u64 *lower_total, int32_t *tpos,
-                             int32_t *err) {
+                             u64 *W, int32_t *err) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nup) return;
-  if (q == 0 && 2 * *lower_total != (u64)nnz) flag_err(err, GC_EASYMMETRIC);
-  const u64 key = sorted[q];
-  const int64_t y = (int64_t)(key >> 32), p = (int64_t)(key & 0xffffffffull);
-  if (y >= n || p >= nnz) {  // only with a count mismatch (keys left unwritten)
-    flag_err(err, GC_EASYMMETRIC);
-    return;
+  const int lane = lane_id();
+  int64_t y = -1 - lane;  // a lane without a pair is a segment of its own
+  u64 len = 0;
+  if (q < nup) {
+    if (q == 0 && 2 * *lower_total != (u64)nnz) flag_err(err, GC_EASYMMETRIC);
+    const u64 key = sorted[q];
+    const int64_t yk = (int64_t)(key >> 32), p = (int64_t)(key & 0xffffffffull);
+    bool ok = yk < n && p < nnz;  // else only with a count mismatch (keys left unwritten)
+    int64_t k = 0;
+    if (ok) {
+      k = q - loff[yk];
+      ok = k >= 0 && k < lcnt[yk];
+    }
+    int32_t lo = 0, x = 0;
+    if (ok) {
+      lo = rp2[yk] + (int32_t)k;
+      x = col2[lo];  // y's k-th lower neighbour: the row of p if symmetric
+      ok = p >= rp2[x] && p < rp2[x + 1];
+    }
+    if (ok) {
+      tpos[lo] = (int32_t)p;
+      tpos[p] = lo;
+      y = yk;
+      len = (u64)(p - rp2[x]);
+    } else {
+      flag_err(err, GC_EASYMMETRIC);
+    }
   }
-  const int64_t k = q - loff[y];
-  if (k < 0 || k >= lcnt[y]) {
-    flag_err(err, GC_EASYMMETRIC);
-    return;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const u64 t = __shfl_down(len, off, kWave);
+    const int64_t ty = __shfl_down(y, off, kWave);
+    if (lane + off < kWave && ty == y) len += t;
   }
-  const int32_t lo = rp2[y] + (int32_t)k;
-  const int32_t x = col2[lo];  // y's k-th lower neighbour: the row of p if symmetric
-  if (p < rp2[x] || p >= rp2[x + 1]) {
-    flag_err(err, GC_EASYMMETRIC);
-    return;
-  }
-  tpos[lo] = (int32_t)p;
-  tpos[p] = lo;
-}
-
-// W[x] = wedges x - v - y with v, y below x: sum over v in L(x) of the length
-// of the prefix of N(v) below x, which ends at tpos[q] (x's own position in
-// N(v)).  One wave per vertex over its lower entries; one write per vertex.
-__global__ __launch_bounds__(256) void k_wedges(const int32_t *rp2, const int32_t *col2,
-                                                const int32_t *lcnt, const int32_t *tpos,
-                                                int64_t n, u64 *W) {
-  const int64_t waves = (int64_t)gridDim.x * (256 / kWave);
-  for (int64_t x = (int64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave; x < n;
-       x += waves) {
-    const int32_t a = rp2[x], l = lcnt[x];
-    u64 s = 0;
-    for (int q = a + lane_id(); q < a + l; q += kWave) s += (u64)(tpos[q] - rp2[col2[q]]);
-    s = wave_sum_u64(s);
-    if (lane_id() == 0) W[x] = s;
-  }
+  const int64_t py = __shfl_up(y, 1, kWave);
+  if (y >= 0 && (lane == 0 || py != y) && len) atomicAdd(&W[y], len);
 }
 
 // Wave-aggregated append of x to list L (counter *cnt): one atomic per wave.
@@ -466,10 +470,9 @@ int run_prepass(PrepassArgs &p, Arena &a, hipStream_t s) {
     u64 *tsorted;
     GC_TRY(radix_sort_u64(tk, tk + nup, nup, B, &tsorted, a, s, 32));
     k_twin_pairs<<<grid1d(nup, 256), 256, 0, s>>>(tsorted, nup, p.rp2, p.col2, p.lcnt, loff, n,
-                                                 nnz, &p.cnt->lower_total, p.tpos, &p.acc->err);
+                                                 nnz, &p.cnt->lower_total, p.tpos, p.W,
+                                                 &p.acc->err);
   }
-  const unsigned wgrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 3) / 4, 16384));
-  k_wedges<<<wgrid, 256, 0, s>>>(p.rp2, p.col2, p.lcnt, p.tpos, n, p.W);
   k_bins<<<grid1d(n, 256), 256, 0, s>>>(p.ucnt, p.lcnt, p.W, n, p.tk[0], p.tk[1], p.tk[2],
                                         p.tk[3], p.tk[4], p.c4l, p.c4m, p.c4h, p.medium_max,
                                         p.cnt);
