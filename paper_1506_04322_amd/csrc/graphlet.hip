@@ -442,11 +442,12 @@ int run(const gc_csr *G, gc_u128 out17[17], int64_t *per_edge_out, int64_t *loca
     GC_TRY_HIP(hipMemcpyAsync(hx.data(), dy.hubs, sizeof(int32_t) * cand, hipMemcpyDeviceToHost, s));
     GC_TRY_HIP(hipMemcpyAsync(hw.data(), dy.hubw, sizeof(u64) * cand, hipMemcpyDeviceToHost, s));
     GC_TRY_HIP(hipStreamSynchronize(s));
+    const double slab_ps = kDenseSlabFixedPs + kDenseSlabEntryPs * (double)nnz;
     for (int b = 0; b < cand; b += kDenseSlab) {
       const int e = std::min(cand, b + kDenseSlab);
       u64 w = 0;
       for (int i = b; i < e; i++) w += hw[i];
-      if (dense_off || (!dense_all && (double)w * kSparseWedgePs < kDenseSlabPs)) break;
+      if (dense_off || (!dense_all && (double)w * kSparseWedgePs < slab_ps)) break;
       std::vector<int32_t> slab(hx.begin() + b, hx.begin() + e);
       std::sort(slab.begin(), slab.end(), std::greater<int32_t>());
       hubs.insert(hubs.end(), slab.begin(), slab.end());

@@ -204,8 +204,13 @@ constexpr int kDenseSlab = 256;        // hubs per slab
 constexpr int kDenseWords = kDenseSlab / 64;  // mask words per vertex
 constexpr int kDenseHubMax = 8192;     // candidates examined by the host
 constexpr int kDenseShortDeg = 1023;   // rows up to this degree: one thread, 10 bit planes
-constexpr double kDenseSlabPs = 2.9e9;      // measured cost of one slab pass (R-MAT s22)
-constexpr double kSparseWedgePs = 2.84;     // measured cost of one heavy wedge by work items
+// Cost model of the route (picoseconds), measured on R-MAT s22: a slab pass
+// reads every adjacency entry and gathers one mask per entry (2.9 ms for
+// 1.28e8 entries, about 20 us of it its four launches); a heavy wedge by work
+// items costs 2.84 ps.
+constexpr double kDenseSlabFixedPs = 2.0e7;
+constexpr double kDenseSlabEntryPs = 22.4;
+constexpr double kSparseWedgePs = 2.84;
 struct HubArgs {
   const int32_t *rp2, *col2, *lcnt;
   int64_t n;
