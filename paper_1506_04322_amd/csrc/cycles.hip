@@ -954,21 +954,37 @@ __global__ __launch_bounds__(256) void k_hub_short(HubArgs g) {
       for (int j = 0; j < kShortBits; j++) P[w][j] = 0;
     const int a = g.rp2[y], b = g.rp2[y + 1];
     int p = a;
-    for (; p + 2 <= b; p += 2) {
-      int v[2];
-      ulonglong2 mm[2][NH];
+    // pairs of entries, the next pair's masks in flight while the current
+    // pair's are added to the planes
+    ulonglong2 mm[2][NH];
+    if (p + 2 <= b) {
 #pragma unroll
-      for (int r = 0; r < 2; r++) v[r] = g.col2[p + r];
+      for (int r = 0; r < 2; r++) {
+        const int v = g.col2[p + r];
+#pragma unroll
+        for (int h = 0; h < NH; h++) mm[r][h] = M[(size_t)v * NH + h];
+      }
+    }
+    for (; p + 2 <= b; p += 2) {
+      ulonglong2 cur[2][NH];
 #pragma unroll
       for (int r = 0; r < 2; r++)
 #pragma unroll
-        for (int h = 0; h < NH; h++) mm[r][h] = M[(size_t)v[r] * NH + h];
+        for (int h = 0; h < NH; h++) cur[r][h] = mm[r][h];
+      if (p + 4 <= b) {
+#pragma unroll
+        for (int r = 0; r < 2; r++) {
+          const int v = g.col2[p + 2 + r];
+#pragma unroll
+          for (int h = 0; h < NH; h++) mm[r][h] = M[(size_t)v * NH + h];
+        }
+      }
 #pragma unroll
       for (int r = 0; r < 2; r++)
 #pragma unroll
         for (int h = 0; h < NH; h++) {
-          if (mm[r][h].x) plane_add(P[2 * h], mm[r][h].x);
-          if (mm[r][h].y) plane_add(P[2 * h + 1], mm[r][h].y);
+          if (cur[r][h].x) plane_add(P[2 * h], cur[r][h].x);
+          if (cur[r][h].y) plane_add(P[2 * h + 1], cur[r][h].y);
         }
     }
     for (; p < b; p++) {
