@@ -1014,10 +1014,14 @@ __global__ __launch_bounds__(256) void k_hub_short(HubArgs g) {
 }
 
 // Rows y of degree > kDenseShortDeg below the slab's top hub, one
-// workgroup each, counters in LDS (a set per wave, added at the end).
+// workgroup each.  Each thread adds a contiguous chunk of at most
+// kDenseShortDeg entries into bit planes, as the short rows do, then adds
+// its per-hub counts into the row's LDS counters (one atomic per hub it
+// saw, not one per entry and hub); rows longer than 256 chunks take several
+// rounds.
 __global__ __launch_bounds__(256) void k_hub_long(HubArgs g) {
   __shared__ int32_t xs[kDenseSlab];
-  __shared__ uint32_t cnt[256 / kWave][kDenseSlab];  // one set per wave: less contention
+  __shared__ uint32_t cnt[kDenseSlab];
   __shared__ u64 red[32];
   __shared__ int s_long;
   for (int k = threadIdx.x; k < g.nslab; k += blockDim.x) xs[k] = g.xs[k];
@@ -1025,32 +1029,52 @@ __global__ __launch_bounds__(256) void k_hub_long(HubArgs g) {
   __syncthreads();
   const int y0 = s_long, ylim = xs[0];
   const ulonglong2 *M = reinterpret_cast<const ulonglong2 *>(g.mask);
+  constexpr int NH = kDenseWords / 2;
+  constexpr int ROUND = 256 * kDenseShortDeg;  // entries per round of the workgroup
   u128 acc = 0;
   for (int y = y0 + blockIdx.x; y < ylim; y += gridDim.x) {
     const int t = hubs_above(xs, g.nslab, y);
     if (t == 0) continue;  // uniform
-    for (int k = threadIdx.x; k < (256 / kWave) * kDenseSlab; k += blockDim.x) cnt[0][k] = 0;
+    for (int k = threadIdx.x; k < kDenseSlab; k += blockDim.x) cnt[k] = 0;
     __syncthreads();
-    uint32_t *mine = cnt[threadIdx.x / kWave];
     const int a = g.rp2[y], b = g.rp2[y + 1];
-    for (int p = a + threadIdx.x; p < b; p += blockDim.x) {
-      const size_t v = (size_t)g.col2[p];
+    for (int r0 = a; r0 < b; r0 += ROUND) {
+      const int len = min(ROUND, b - r0);
+      const int L = (len + 255) / 256;  // <= kDenseShortDeg: no plane overflows
+      const int c0 = r0 + (int)threadIdx.x * L, c1 = min(r0 + len, c0 + L);
+      u64 P[kDenseWords][kShortBits];
+#pragma unroll
+      for (int w = 0; w < kDenseWords; w++)
+#pragma unroll
+        for (int j = 0; j < kShortBits; j++) P[w][j] = 0;
+      for (int p = c0; p < c1; p++) {
+        const int v = g.col2[p];
+#pragma unroll
+        for (int h = 0; h < NH; h++) {
+          const ulonglong2 mm = M[(size_t)v * NH + h];
+          if (mm.x) plane_add(P[2 * h], mm.x);
+          if (mm.y) plane_add(P[2 * h + 1], mm.y);
+        }
+      }
 #pragma unroll
       for (int w = 0; w < kDenseWords; w++) {
-        u64 m = g.mask[kDenseWords * v + w];
-        while (m) {
-          const int k = 64 * w + __builtin_ctzll(m);
-          m &= m - 1;
-          if (k < t) atomicAdd(&mine[k], 1u);
+        const int tw = t - 64 * w;
+        u64 any = 0;
+#pragma unroll
+        for (int j = 0; j < kShortBits; j++) any |= P[w][j];
+        any &= tw >= 64 ? ~0ull : (tw > 0 ? ((1ull << tw) - 1) : 0ull);
+        while (any) {
+          const int bit = __builtin_ctzll(any);
+          any &= any - 1;
+          uint32_t c = 0;
+#pragma unroll
+          for (int j = 0; j < kShortBits; j++) c |= (uint32_t)((P[w][j] >> bit) & 1ull) << j;
+          atomicAdd(&cnt[64 * w + bit], c);
         }
       }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < t; k += blockDim.x) {
-      u64 c = 0;
-      for (int w = 0; w < 256 / kWave; w++) c += cnt[w][k];
-      acc += (u128)choose2(c);
-    }
+    for (int k = threadIdx.x; k < t; k += blockDim.x) acc += (u128)choose2(cnt[k]);
     __syncthreads();
   }
   const u128 s = block_sum_u128(acc, red);
