@@ -205,11 +205,11 @@ constexpr int kDenseWords = kDenseSlab / 64;  // mask words per vertex
 constexpr int kDenseHubMax = 8192;     // candidates examined by the host
 constexpr int kDenseShortDeg = 1023;   // rows up to this degree: one thread, 10 bit planes
 // Cost model of the route (picoseconds), measured on R-MAT s22: a slab pass
-// reads every adjacency entry and gathers one mask per entry (2.9 ms for
+// reads every adjacency entry and gathers one mask per entry (2.63 ms for
 // 1.28e8 entries, about 20 us of it its four launches); a heavy wedge by work
 // items costs 2.84 ps.
 constexpr double kDenseSlabFixedPs = 2.0e7;
-constexpr double kDenseSlabEntryPs = 22.4;
+constexpr double kDenseSlabEntryPs = 20.3;
 constexpr double kSparseWedgePs = 2.84;
 struct HubArgs {
   const int32_t *rp2, *col2, *lcnt;
