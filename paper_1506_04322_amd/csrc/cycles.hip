@@ -190,17 +190,29 @@ __global__ __launch_bounds__(kMediumBlock) void k_c4_medium(C4Args g) {
       __syncthreads();
       scan_excl<kMediumBlock>(sPre, nb, sums);
       const int total = sPre[nb];
-      for (int t = tid; t < total; t += kMediumBlock) {
-        const int o = upper_index_dev<int32_t>(sPre, nb, t);
-        const int y = g.col2[sStart[o] + (t - sPre[o])];
-        int h = (int)(((u64)((uint32_t)y * 2654435761u) * (u64)hs) >> 32);
-        while (true) {
-          const int old = atomicCAS(&hkey[h], -1, y);
-          if (old == -1 || old == y) {
-            atomicAdd(&hcnt[h >> 1], (h & 1) ? 65536u : 1u);
-            break;
+      // each thread takes a contiguous range of the wedges: one search for
+      // the list of its first, then a cursor
+      const int per = (total + kMediumBlock - 1) / kMediumBlock;
+      const int t0 = tid * per, t1 = min(total, t0 + per);
+      if (t0 < t1) {
+        int o = upper_index_dev<int32_t>(sPre, nb, t0);
+        int lo = sPre[o], next = sPre[o + 1];
+        for (int t = t0; t < t1; t++) {
+          while (t >= next) {  // ends: t < total = sPre[nb]
+            o++;
+            lo = next;
+            next = sPre[o + 1];
           }
-          h = h + 1 == hs ? 0 : h + 1;
+          const int y = g.col2[sStart[o] + (t - lo)];
+          int h = (int)(((u64)((uint32_t)y * 2654435761u) * (u64)hs) >> 32);
+          while (true) {
+            const int old = atomicCAS(&hkey[h], -1, y);
+            if (old == -1 || old == y) {
+              atomicAdd(&hcnt[h >> 1], (h & 1) ? 65536u : 1u);
+              break;
+            }
+            h = h + 1 == hs ? 0 : h + 1;
+          }
         }
       }
       __syncthreads();
