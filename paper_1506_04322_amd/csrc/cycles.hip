@@ -230,17 +230,33 @@ __global__ __launch_bounds__(kMediumBlock) void k_c4_medium(C4Args g) {
         __syncthreads();
         scan_excl<kMediumBlock>(sPre, nb, sums);
         const int total = sPre[nb];
-        for (int t = tid; t < total; t += kMediumBlock) {
-          const int o = upper_index_dev<int32_t>(sPre, nb, t);
-          const int p = sStart[o] + (t - sPre[o]);
-          const int y = g.col2[p];
-          int h = (int)(((u64)((uint32_t)y * 2654435761u) * (u64)hs) >> 32);
-          while (hkey[h] != y) h = h + 1 == hs ? 0 : h + 1;  // y was inserted above
-          const uint32_t c = (hcnt[h >> 1] >> ((h & 1) * 16)) & 0xffffu;
-          if (c >= 2) {
-            atomicAdd(&g.C4w[p], (u64)(c - 1));
-            atomicAdd(&credit[o], (u64)(c - 1));
+        // contiguous ranges and a list cursor, as in the count above; the
+        // credits of edge (x, v) gather in a register while the list lasts
+        const int per = (total + kMediumBlock - 1) / kMediumBlock;
+        const int t0 = tid * per, t1 = min(total, t0 + per);
+        if (t0 < t1) {
+          int o = upper_index_dev<int32_t>(sPre, nb, t0);
+          int lo = sPre[o], next = sPre[o + 1];
+          u64 cr = 0;
+          for (int t = t0; t < t1; t++) {
+            while (t >= next) {  // ends: t < total = sPre[nb]
+              if (cr) atomicAdd(&credit[o], cr);
+              cr = 0;
+              o++;
+              lo = next;
+              next = sPre[o + 1];
+            }
+            const int p = sStart[o] + (t - lo);
+            const int y = g.col2[p];
+            int h = (int)(((u64)((uint32_t)y * 2654435761u) * (u64)hs) >> 32);
+            while (hkey[h] != y) h = h + 1 == hs ? 0 : h + 1;  // y was inserted above
+            const uint32_t c = (hcnt[h >> 1] >> ((h & 1) * 16)) & 0xffffu;
+            if (c >= 2) {
+              atomicAdd(&g.C4w[p], (u64)(c - 1));
+              cr += c - 1;
+            }
           }
+          if (cr) atomicAdd(&credit[o], cr);
         }
         __syncthreads();
         if (tid < nb && credit[tid]) atomicAdd(&g.C4w[Lx + b + tid], credit[tid]);
