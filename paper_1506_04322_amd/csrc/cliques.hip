@@ -161,8 +161,8 @@ __attribute__((amdgpu_waves_per_eu(BLOCK <= 512 ? 8 : 1))) void k_tk_up(TkArgs g
   constexpr int RWORDS = 32 * WC * (WC + 1);  // tri_off(64 WC, WC)
   // candidates per lane per slab, all loaded before any is probed; the
   // 1024-thread shape is held to 4 waves per SIMD by LDS, not registers, so
-  // it keeps twice as many loads in flight
-  constexpr int RUN = BLOCK == 1024 ? 16 : 6;
+  // it keeps four times as many loads in flight (24 still fits in 128 VGPRs)
+  constexpr int RUN = BLOCK == 1024 ? 24 : 6;
   // filter of U(u): 8 bits per hash slot (4 for the two largest tables),
   // so at most 1 in 32 candidates outside U(u) reaches the hash table
   constexpr int FLOG = (31 - __builtin_clz(HS)) + (HS <= 1024 ? 3 : 2);
