@@ -45,7 +45,8 @@ extern "C" {
 
 /* Error codes. */
 #define GC_OK 0
-#define GC_EINVAL (-1)       /* bad argument: null pointer, negative size, odd nnz */
+#define GC_EINVAL (-1)       /* bad argument: null pointer, negative size, odd nnz,
+                                 entries with no vertices */
 #define GC_ENOTSORTED (-2)   /* a neighbour list is not strictly increasing (covers duplicates) */
 #define GC_ESELFLOOP (-3)    /* (u, u) present */
 #define GC_EASYMMETRIC (-4)  /* v in N(u) but u not in N(v), or an id outside [0, n) */

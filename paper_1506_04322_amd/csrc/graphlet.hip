@@ -666,7 +666,8 @@ int check_args(const gc_csr *g) {
     set_error("null graph");
     return GC_EINVAL;
   }
-  if (g->n < 0 || g->nnz < 0 || g->n > 2147483646LL || g->nnz > 2147483646LL || (g->nnz & 1)) {
+  if (g->n < 0 || g->nnz < 0 || g->n > 2147483646LL || g->nnz > 2147483646LL || (g->nnz & 1) ||
+      (g->n == 0 && g->nnz > 0)) {
     set_error("invalid sizes n=%lld nnz=%lld", (long long)g->n, (long long)g->nnz);
     return GC_EINVAL;
   }

@@ -75,22 +75,85 @@ __global__ void k_rank(const u64 *sorted, int64_t n, int B, int32_t *order, int3
   deg2[x] = (int32_t)(k >> B);
 }
 
-// One wave per row: key (rank[u] << B | rank[w]) for every entry.  An id
-// outside [0, n) (broken contract, no validation) is flagged, never indexed.
-__global__ void k_edge_keys(const int32_t *rp, const int32_t *col, int64_t n, int B,
-                            const int32_t *rank, u64 *ekeys, int32_t *err) {
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
-  const int lane = lane_id();
-  for (int64_t u = wave; u < n; u += nwaves) {
-    const u64 ru = (u64)rank[u] << B;
-    for (int64_t j = rp[u] + lane; j < rp[u + 1]; j += kWave) {
-      int32_t w = col[j];
+// Edge keys (rank[u] << B | rank[w]) for every entry, in tiles of kEkTile
+// consecutive entries.  The row of each entry comes from the row starts that
+// fall inside the tile, marked in LDS and carried forward by a prefix max, so
+// the entries are read and the keys written in order whatever the row
+// lengths.  tilerow[t] is the row that holds entry t kEkTile, and
+// tilerow[ntiles] the row of the last entry, both written by k_tile_rows;
+// rows, tiles and ids are clamped, so a row_ptr that breaks the
+// contract (unchecked without validation) gives wrong keys, never an access
+// outside the arrays.  An id outside [0, n) is flagged and never indexed.
+constexpr int kEkBlock = 256;
+constexpr int kEkIpt = 8;
+constexpr int kEkTile = kEkBlock * kEkIpt;
+
+__global__ void k_tile_rows(const int32_t *rp, int64_t n, int64_t nnz, int64_t ntiles,
+                            int32_t *tilerow) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
+    const int64_t a = rp[u], b = min((int64_t)rp[u + 1], nnz);
+    if (a < 0 || a >= b) continue;
+    for (int64_t t = (a + kEkTile - 1) / kEkTile; t * kEkTile < b; t++) tilerow[t] = (int32_t)u;
+    if (b == nnz) tilerow[ntiles] = (int32_t)u;
+  }
+}
+
+__global__ __launch_bounds__(kEkBlock) void k_edge_keys(const int32_t *rp, const int32_t *col,
+                                                        int64_t n, int64_t nnz, int B,
+                                                        const int32_t *rank,
+                                                        const int32_t *tilerow, u64 *ekeys,
+                                                        int32_t *err) {
+  __shared__ int32_t rowat[kEkTile];
+  __shared__ int32_t wmax[kEkBlock / kWave];
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+  const int64_t t = blockIdx.x, ntiles = gridDim.x;
+  const int64_t jb = t * kEkTile;
+  const int cnt = (int)min((int64_t)kEkTile, nnz - jb);
+  const int64_t uf = min(max((int64_t)tilerow[t], (int64_t)0), n - 1);
+  const int64_t ul = min(max((int64_t)tilerow[t + 1], uf), n - 1);
+#pragma unroll
+  for (int r = 0; r < kEkIpt; r++) rowat[r * kEkBlock + tid] = r == 0 && tid == 0 ? (int32_t)uf : -1;
+  __syncthreads();
+  // rows after the tile's first row that start inside the tile (an empty row
+  // starts where the next row does and is skipped)
+  for (int64_t u = uf + 1 + tid; u <= ul; u += kEkBlock) {
+    const int64_t a = rp[u], b = rp[u + 1];
+    if (a >= jb && a < jb + cnt && b > a) rowat[a - jb] = (int32_t)u;
+  }
+  __syncthreads();
+  // inclusive prefix max over the tile: kEkIpt consecutive slots per thread
+  int32_t v[kEkIpt], m = -1;
+#pragma unroll
+  for (int r = 0; r < kEkIpt; r++) {
+    m = max(m, rowat[tid * kEkIpt + r]);
+    v[r] = m;
+  }
+  int32_t incl = m;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int32_t o = __shfl_up(incl, off, kWave);
+    if (lane >= off) incl = max(incl, o);
+  }
+  if (lane == kWave - 1) wmax[wave] = incl;
+  __syncthreads();
+  int32_t before = __shfl_up(incl, 1, kWave);
+  if (lane == 0) before = -1;
+  for (int w = 0; w < wave; w++) before = max(before, wmax[w]);
+#pragma unroll
+  for (int r = 0; r < kEkIpt; r++) rowat[tid * kEkIpt + r] = max(v[r], before);
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kEkIpt; r++) {
+    const int i = r * kEkBlock + tid;
+    if (i < cnt) {
+      const int32_t u = rowat[i];
+      int32_t w = col[jb + i];
       if (w < 0 || w >= n) {
         flag_err(err, GC_EASYMMETRIC);
-        w = (int32_t)u;
+        w = u;
       }
-      ekeys[j] = ru | (u64)rank[w];
+      ekeys[jb + i] = ((u64)rank[u] << B) | (u64)rank[w];
     }
   }
 }
@@ -443,9 +506,16 @@ int run_prepass(PrepassArgs &p, Arena &a, hipStream_t s) {
   GC_TRY_HIP(hipGetLastError());
   GC_TRY(scan_exclusive<int32_t>(p.deg2, p.rp2, n, a, s));
   GC_TRY(fill<int32_t>(p.rp2 + n, (int32_t)nnz, 1, s));
-  k_edge_keys<<<grid1d(n * kWave, 256, 65536), 256, 0, s>>>(p.row_ptr, p.col, n, B, p.rank,
-                                                           p.ekeys, &p.acc->err);
-  GC_TRY_HIP(hipGetLastError());
+  if (nnz > 0) {
+    // the ntiles + 1 tile rows live in the sort's second key buffer (nnz
+    // words of 8 bytes) until the sort
+    const int64_t ntiles = (nnz + kEkTile - 1) / kEkTile;
+    int32_t *tilerow = reinterpret_cast<int32_t *>(p.ekeys_alt);
+    k_tile_rows<<<grid1d(n, 256), 256, 0, s>>>(p.row_ptr, n, nnz, ntiles, tilerow);
+    k_edge_keys<<<(unsigned)ntiles, kEkBlock, 0, s>>>(p.row_ptr, p.col, n, nnz, B, p.rank, tilerow,
+                                                      p.ekeys, &p.acc->err);
+    GC_TRY_HIP(hipGetLastError());
+  }
   GC_TRY(radix_sort_u64(p.ekeys, p.ekeys_alt, nnz, 2 * B, &p.esorted, a, s));
   k_split_keys<<<grid1d(nnz, 256), 256, 0, s>>>(p.esorted, nnz, B, p.col2, p.tpos);
   k_split_rows<<<grid1d(n, 256), 256, 0, s>>>(p.rp2, p.col2, n, p.lcnt, p.ucnt, p.ustart,

@@ -46,6 +46,10 @@ def test_null_arguments_are_rejected_without_touching_a_device():
     assert lib.graphlet_workspace_size(None, 0, None) == 0
     bad = gl._Csr(5, 3, 0, 0)  # odd nnz
     assert lib.graphlet_count(ctypes.byref(bad), (gl._U128 * 17)(), None, None, 0, None, 0) == -1
+    # entries with no vertices: refused from the sizes (pointers never read)
+    bad = gl._Csr(0, 2, 0x1000, 0x1000)
+    assert lib.graphlet_count(ctypes.byref(bad), (gl._U128 * 17)(), None, None, 0, None, 0) == -1
+    assert "invalid sizes" in gl.graphlet_last_error()
     assert lib.graphlet_count_batched(None, None, None, 0) == -1
     assert lib.graphlet_batch_vertex(None, None, None, 0) == -1
     assert lib.graphlet_count_vertex(None, (gl._U128 * 17)(), None, None, 0, None, 0) == -1
