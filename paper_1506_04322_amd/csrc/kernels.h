@@ -97,7 +97,11 @@ struct Counters {
 
 __device__ __forceinline__ void flag_err(int32_t *err, int code) { atomicOr(err, 1 << (-code)); }
 
-inline unsigned grid1d(int64_t n, int block, int64_t cap = 1 << 20) {
+// Blocks for n items of one thread each.  A cap is for kernels that loop
+// over their items; without one the grid covers every item, as the
+// one-thread-per-item kernels need (n < 2^31 keeps the grid below 2^32
+// work-items).
+inline unsigned grid1d(int64_t n, int block, int64_t cap = INT64_MAX) {
   int64_t g = (n + block - 1) / block;
   if (g < 1) g = 1;
   if (g > cap) g = cap;

@@ -49,18 +49,46 @@ __global__ void k_check_rowptr_ends(const int32_t *rp, int64_t n, int64_t nnz, i
 }
 
 // deg[u] and the key (deg << B | u) ordering vertices by (degree, id).
-__global__ void k_degree_keys(const int32_t *rp, int64_t n, int B, int32_t *deg, u64 *key,
-                              int32_t *max_deg) {
-  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// A capped grid walks the vertices, so the maxima and sums below take one
+// atomic per block (a per-wave atomic on one address serialises thousands).
+constexpr int kRedBlock = 256;
+constexpr int kRedGrid = 2048;
+
+template <class T, class Op>
+__device__ __forceinline__ T block_reduce(T v, Op op, T *sh) {
+  for (int off = 32; off > 0; off >>= 1) v = op(v, __shfl_xor(v, off, kWave));
+  const int wave = threadIdx.x / kWave;
+  __syncthreads();  // sh may still be read by an earlier call
+  if (lane_id() == 0) sh[wave] = v;
+  __syncthreads();
+  T r = sh[0];
+  for (int w = 1; w < (int)(blockDim.x / kWave); w++) r = op(r, sh[w]);
+  return r;
+}
+
+struct MaxOp {
+  template <class T>
+  __device__ T operator()(T a, T b) const { return a > b ? a : b; }
+};
+struct AddOp {
+  template <class T>
+  __device__ T operator()(T a, T b) const { return a + b; }
+};
+
+__global__ __launch_bounds__(kRedBlock) void k_degree_keys(const int32_t *rp, int64_t n, int B,
+                                                           int32_t *deg, u64 *key,
+                                                           int32_t *max_deg) {
+  __shared__ int sh[kRedBlock / kWave];
   int mx = 0;
-  if (u < n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
     const int d = rp[u + 1] - rp[u];
     deg[u] = d;
     key[u] = ((u64)d << B) | (u64)u;
-    mx = d;
+    mx = max(mx, d);
   }
-  for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, kWave));
-  if (lane_id() == 0 && mx) atomicMax(max_deg, mx);
+  mx = block_reduce(mx, MaxOp(), sh);
+  if (threadIdx.x == 0 && mx) atomicMax(max_deg, mx);
 }
 
 // order[x] = caller's id of new vertex x; rank[old] = x; deg2[x] = degree.
@@ -172,28 +200,33 @@ __global__ void k_split_keys(const u64 *ekeys, int64_t nnz, int B, int32_t *col2
 // Also sums |L(x)| over all x (nnz / 2 for a symmetric CSR) and the entries
 // the clique pass scans: vertex v reads U(x) for every x in U(v), i.e.
 // |L(x)| |U(x)| summed over x.
-__global__ void k_split_rows(const int32_t *rp2, const int32_t *col2, int64_t n, int32_t *lcnt,
-                             int32_t *ucnt, int32_t *ustart, int32_t *max_ucnt, u64 *lower_total,
-                             u64 *clique_entries) {
-  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kRedBlock) void k_split_rows(const int32_t *rp2, const int32_t *col2,
+                                                          int64_t n, int32_t *lcnt, int32_t *ucnt,
+                                                          int32_t *ustart, int32_t *max_ucnt,
+                                                          u64 *lower_total, u64 *clique_entries) {
+  __shared__ int shm[kRedBlock / kWave];
+  __shared__ u64 shs[kRedBlock / kWave];
   int mx = 0;
   u64 lsum = 0, ce = 0;
-  if (x < n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += stride) {
     const int a = rp2[x], d = rp2[x + 1] - a;
     const int l = lower_bound_dev<int32_t>(col2 + a, d, (int32_t)x);
     lcnt[x] = l;
     ucnt[x] = d - l;
     ustart[x] = a + l;
-    mx = d - l;
-    lsum = (u64)l;
-    ce = (u64)l * (u64)(d - l);
+    mx = max(mx, d - l);
+    lsum += (u64)l;
+    ce += (u64)l * (u64)(d - l);
   }
-  for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, kWave));
-  lsum = wave_sum_u64(lsum);
-  ce = wave_sum_u64(ce);
-  if (lane_id() == 0 && mx) atomicMax(max_ucnt, mx);
-  if (lane_id() == 0 && lsum) atomicAdd(lower_total, lsum);
-  if (lane_id() == 0 && ce) atomicAdd(clique_entries, ce);
+  mx = block_reduce(mx, MaxOp(), shm);
+  lsum = block_reduce(lsum, AddOp(), shs);
+  ce = block_reduce(ce, AddOp(), shs);
+  if (threadIdx.x == 0) {
+    if (mx) atomicMax(max_ucnt, mx);
+    if (lsum) atomicAdd(lower_total, lsum);
+    if (ce) atomicAdd(clique_entries, ce);
+  }
 }
 
 // Twin positions (tpos[p] = position of the reverse entry) by a stable sort
@@ -271,61 +304,85 @@ __global__ void k_twin_pairs(const u64 *sorted, int64_t nup, const int32_t *rp2,
   if (y >= 0 && (lane == 0 || py != y) && len) atomicAdd(&W[y], len);
 }
 
-// Wave-aggregated append of x to list L (counter *cnt): one atomic per wave.
-__device__ __forceinline__ void wave_append(bool cond, int32_t x, int32_t *list, int32_t *cnt) {
-  const u64 mask = __ballot(cond);
-  if (!mask) return;
-  const int leader = __ffsll((long long)mask) - 1;
-  int base = 0;
-  if (lane_id() == leader) base = atomicAdd(cnt, __popcll(mask));
-  base = __shfl(base, leader, kWave);
-  if (cond) list[base + __popcll(mask & lanemask_lt())] = x;
-}
+// Vertex bins: the clique classes by |U(x)|, the 4-cycle classes by W[x].
+// A block of kBinsBlock vertices reserves its places in each of the eight
+// lists with one atomic per list (per-wave atomics on eight counters
+// serialise by the thousand), and a vertex's place is the block's base plus
+// the members in lower waves and lower lanes.
+constexpr int kBinsBlock = 1024;
+constexpr int kBinsLists = 8;
 
-// Work lists: clique classes by |U(u)| (>= 2), wedge vertices light/heavy.
-__global__ __launch_bounds__(256) void k_bins(const int32_t *ucnt, const int32_t *lcnt,
-                                              const u64 *W, int64_t n, int32_t *tk0, int32_t *tk1,
-                                              int32_t *tk2, int32_t *tk3, int32_t *tk4,
-                                              int32_t *c4l, int32_t *c4m, int32_t *c4h,
-                                              u64 medium_max, Counters *cnt) {
-  __shared__ u64 red[3][4];
+__global__ __launch_bounds__(kBinsBlock) void k_bins(const int32_t *ucnt, const int32_t *lcnt,
+                                                     const u64 *W, int64_t n, int32_t *tk0,
+                                                     int32_t *tk1, int32_t *tk2, int32_t *tk3,
+                                                     int32_t *tk4, int32_t *c4l, int32_t *c4m,
+                                                     int32_t *c4h, u64 medium_max,
+                                                     Counters *cnt) {
+  constexpr int NW = kBinsBlock / kWave;
+  __shared__ int32_t off[kBinsLists][NW];
+  __shared__ int shm[NW];
+  __shared__ u64 shs[NW];
+  const int wave = threadIdx.x / kWave, lane = lane_id();
   const int64_t xi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool in = xi < n;
   const int32_t x = (int32_t)xi;
   const int k = in ? ucnt[x] : 0;
   const u64 w = in ? W[x] : 0;
   const int cls = k >= 2 ? tk_class(k) : -1;
-  wave_append(cls == 0, x, tk0, &cnt->tk_cnt[0]);
-  wave_append(cls == 1, x, tk1, &cnt->tk_cnt[1]);
-  wave_append(cls == 2, x, tk2, &cnt->tk_cnt[2]);
-  wave_append(cls == 3, x, tk3, &cnt->tk_cnt[3]);
-  wave_append(cls == 4, x, tk4, &cnt->tk_cnt[4]);
-  const u64 gslot = __ballot(cls == 3 && k > kTkPeLds);
-  if (lane_id() == 0 && gslot) atomicAdd(&cnt->tk_pe_global, __popcll(gslot));
   const bool light = w >= 2 && w <= kLightWedges;  // one wedge cannot close a cycle
   const bool medium = w > kLightWedges && w <= medium_max;
   const bool heavy = w > medium_max && w > kLightWedges;
-  wave_append(light, x, c4l, &cnt->c4_light);
-  wave_append(medium, x, c4m, &cnt->c4_medium);
-  wave_append(heavy, x, c4h, &cnt->c4_heavy);
-  int ml = heavy ? lcnt[x] : 0;
-  for (int off = 32; off > 0; off >>= 1) ml = max(ml, __shfl_xor(ml, off, kWave));
-  if (lane_id() == 0 && ml) atomicMax(&cnt->max_lcnt_heavy, ml);
-  const u64 wl = wave_sum_u64(light ? w : 0), wm = wave_sum_u64(medium ? w : 0),
-            wh = wave_sum_u64(heavy ? w : 0);
-  if (lane_id() == 0) {
-    red[0][threadIdx.x / kWave] = wl;
-    red[1][threadIdx.x / kWave] = wh;
-    red[2][threadIdx.x / kWave] = wm;
+  // list i: clique class i for i < 5, then light, medium and heavy x
+  u64 bal[kBinsLists];
+#pragma unroll
+  for (int i = 0; i < 5; i++) bal[i] = __ballot(cls == i);
+  bal[5] = __ballot(light);
+  bal[6] = __ballot(medium);
+  bal[7] = __ballot(heavy);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < kBinsLists; i++) off[i][wave] = __popcll(bal[i]);
   }
   __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kBinsLists; i++) {
+    if ((int)threadIdx.x == i) {
+      int sum = 0;
+      for (int v = 0; v < NW; v++) {
+        const int c = off[i][v];
+        off[i][v] = sum;
+        sum += c;
+      }
+      int32_t *ctr = i < 5 ? &cnt->tk_cnt[i] : i == 5 ? &cnt->c4_light : i == 6 ? &cnt->c4_medium
+                                                                               : &cnt->c4_heavy;
+      const int base = sum ? atomicAdd(ctr, sum) : 0;
+      for (int v = 0; v < NW; v++) off[i][v] += base;
+    }
+  }
+  __syncthreads();
+  const u64 lt = lanemask_lt();
+  if (cls >= 0) {
+    int32_t *L = cls == 0 ? tk0 : cls == 1 ? tk1 : cls == 2 ? tk2 : cls == 3 ? tk3 : tk4;
+    u64 b = bal[0];
+#pragma unroll
+    for (int i = 1; i < 5; i++)
+      if (cls == i) b = bal[i];
+    L[off[cls][wave] + __popcll(b & lt)] = x;
+  }
+  if (light) c4l[off[5][wave] + __popcll(bal[5] & lt)] = x;
+  if (medium) c4m[off[6][wave] + __popcll(bal[6] & lt)] = x;
+  if (heavy) c4h[off[7][wave] + __popcll(bal[7] & lt)] = x;
+  const int gs = block_reduce((cls == 3 && k > kTkPeLds) ? 1 : 0, AddOp(), shm);
+  const int ml = block_reduce(heavy ? lcnt[x] : 0, MaxOp(), shm);
+  const u64 wl = block_reduce(light ? w : 0, AddOp(), shs);
+  const u64 wm = block_reduce(medium ? w : 0, AddOp(), shs);
+  const u64 wh = block_reduce(heavy ? w : 0, AddOp(), shs);
   if (threadIdx.x == 0) {
-    const u64 a = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-    const u64 b = red[1][0] + red[1][1] + red[1][2] + red[1][3];
-    const u64 c = red[2][0] + red[2][1] + red[2][2] + red[2][3];
-    if (a) atomicAdd(&cnt->wedges_light, a);
-    if (b) atomicAdd(&cnt->wedges_heavy, b);
-    if (c) atomicAdd(&cnt->wedges_medium, c);
+    if (gs) atomicAdd(&cnt->tk_pe_global, gs);
+    if (ml) atomicMax(&cnt->max_lcnt_heavy, ml);
+    if (wl) atomicAdd(&cnt->wedges_light, wl);
+    if (wh) atomicAdd(&cnt->wedges_heavy, wh);
+    if (wm) atomicAdd(&cnt->wedges_medium, wm);
   }
 }
 
@@ -496,7 +553,8 @@ int launch_validate(const int32_t *rp, const int32_t *col, int64_t n, int64_t nn
 int run_prepass(PrepassArgs &p, Arena &a, hipStream_t s) {
   const int64_t n = p.n, nnz = p.nnz;
   const int B = p.B;
-  k_degree_keys<<<grid1d(n, 256), 256, 0, s>>>(p.row_ptr, n, B, p.deg, p.rkeys, &p.cnt->max_deg);
+  k_degree_keys<<<grid1d(n, kRedBlock, kRedGrid), kRedBlock, 0, s>>>(p.row_ptr, n, B, p.deg, p.rkeys,
+                                                                     &p.cnt->max_deg);
   GC_TRY_HIP(hipGetLastError());
   u64 *rsorted;
   // the keys are made in id order, so a stable sort on the degree bits alone
@@ -518,9 +576,9 @@ int run_prepass(PrepassArgs &p, Arena &a, hipStream_t s) {
   }
   GC_TRY(radix_sort_u64(p.ekeys, p.ekeys_alt, nnz, 2 * B, &p.esorted, a, s));
   k_split_keys<<<grid1d(nnz, 256), 256, 0, s>>>(p.esorted, nnz, B, p.col2, p.tpos);
-  k_split_rows<<<grid1d(n, 256), 256, 0, s>>>(p.rp2, p.col2, n, p.lcnt, p.ucnt, p.ustart,
-                                              &p.cnt->max_ucnt, &p.cnt->lower_total,
-                                              &p.cnt->clique_entries);
+  k_split_rows<<<grid1d(n, kRedBlock, kRedGrid), kRedBlock, 0, s>>>(
+      p.rp2, p.col2, n, p.lcnt, p.ucnt, p.ustart, &p.cnt->max_ucnt, &p.cnt->lower_total,
+      &p.cnt->clique_entries);
   {
     // twin positions: the upper entries sorted by target (the other edge-key
     // buffer, free after the edge sort, holds the keys and their second
@@ -543,9 +601,9 @@ int run_prepass(PrepassArgs &p, Arena &a, hipStream_t s) {
                                                  nnz, &p.cnt->lower_total, p.tpos, p.W,
                                                  &p.acc->err);
   }
-  k_bins<<<grid1d(n, 256), 256, 0, s>>>(p.ucnt, p.lcnt, p.W, n, p.tk[0], p.tk[1], p.tk[2],
-                                        p.tk[3], p.tk[4], p.c4l, p.c4m, p.c4h, p.medium_max,
-                                        p.cnt);
+  k_bins<<<grid1d(n, kBinsBlock), kBinsBlock, 0, s>>>(p.ucnt, p.lcnt, p.W, n, p.tk[0], p.tk[1],
+                                                      p.tk[2], p.tk[3], p.tk[4], p.c4l, p.c4m,
+                                                      p.c4h, p.medium_max, p.cnt);
   GC_TRY_HIP(hipGetLastError());
   return GC_OK;
 }
