@@ -35,8 +35,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 # 32-bit integer vector lane operations per second: 256 compute units x 4
-# SIMDs x 16 lanes per clock x 2.4 GHz (the fp32 vector rate of 78.6 TFLOP/s
-# counts an FMA as two operations; integer AND / popcount are one each)
+# SIMDs x 16 lanes per clock x 2.4 GHz (the fp32 vector rate of 157.3 TFLOP/s
+# is twice this for an FMA's two operations and twice again for packed fp32;
+# integer AND and popcount are one operation on one lane each)
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
