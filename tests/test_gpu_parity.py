@@ -86,6 +86,28 @@ def test_isolated_vertices_many():
     check_full(g)
 
 
+def test_edge_keys_ragged_tiles():
+    # the prepass keys the entries in tiles of 2048 consecutive entries: a
+    # row that starts inside a tile and spans several, runs of empty rows
+    # between rows, nnz an exact multiple of the tile, a lone edge at the
+    # last ids, trailing isolated vertices
+    rng = np.random.default_rng(77)
+    n = 9000
+    ids = [int(v) for v in rng.permutation(n)[:2400]]
+    hub, leaves = ids[0], ids[1:2101]
+    edges = [(hub, v) for v in leaves]
+    edges += [(leaves[i], leaves[i + 1]) for i in range(0, 600, 2)]
+    edges += list(zip(ids[2101:2250], ids[2250:2399]))
+    g = graphgen.from_edges(n + 500, edges)
+    assert g.nnz > 4096 and np.diff(g.row_ptr).max() > 2048
+    check_full(g)
+    g = graphgen.from_edges(2388, [(300 + i, 300 + (i + 1) % 2048) for i in range(2048)])
+    assert g.nnz == 2 * 2048
+    check_full(g)
+    g = graphgen.from_edges(5000, [(4998, 4999)])
+    check_full(g)
+
+
 def clique_classes(g, per_edge):
     """Runs the graph with timing on; returns the vertex counts per clique
     kernel class (gc_timing.clique_class) and the results."""
